@@ -1,0 +1,283 @@
+/*
+ * ebic.h -- C ABI of libebic, an MI355X (gfx950) implementation of the
+ * population evaluation at the heart of EBIC (Orzechowski, Sipper, Huang &
+ * Moore, "EBIC: an evolutionary-based parallel biclustering algorithm for
+ * pattern discovery", Bioinformatics 2018) and of the evolutionary run that
+ * drives it.
+ *
+ * Conventions
+ *   - Every entry point returns ebic_status; EBIC_OK (0) is success.  No
+ *     exception crosses the ABI.  On error, outputs are left untouched and
+ *     ebic_last_error(ctx) holds a message.
+ *   - Pointers documented as "host" are read or written by the CPU; "device"
+ *     pointers are HIP device allocations on the context's device.
+ *   - A context is not thread-safe: serialise calls on one context.
+ *     Distinct contexts are independent.
+ *   - Matrix values are IEEE binary32.  Any value is legal: NaN compares
+ *     false against everything and +0 equals -0, so pairs holding NaN or a
+ *     tie break both directions.
+ *
+ * Population wire format -- CBF, the Compressed Bicluster Format of Fig. 2:
+ *   offsets  int32[P+1]   offsets[0] = 0, offsets[c+1] > offsets[c],
+ *                         offsets[P] = total number of column entries
+ *   cols     int32[offsets[P]]  0-based column indices; candidate c is the
+ *                         ordered series cols[offsets[c] .. offsets[c+1])
+ *
+ * Row masks: masks[(c*2 + dir)*W + w], W = ebic_mask_words(n_rows), dir 0 =
+ * rows following the rising trend, dir 1 = rows following the falling trend,
+ * bit (r % 64) of word r / 64 set when row r matches; bits of rows >= n_rows
+ * are zero.
+ */
+#ifndef EBIC_H
+#define EBIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ebic_ctx ebic_ctx;
+typedef struct ebic_result ebic_result;
+
+typedef enum {
+    EBIC_OK = 0,
+    EBIC_E_ARG = 1,     /* null pointer, bad size, malformed CBF, duplicate column */
+    EBIC_E_RANGE = 2,   /* column outside [0, n_cols), sigma < 0, max_violations < 0 */
+    EBIC_E_NOMEM = 3,   /* device or host allocation failed */
+    EBIC_E_DEVICE = 4,  /* a HIP call failed; see ebic_last_error */
+    EBIC_E_STATE = 5    /* call not valid in the context's current state */
+} ebic_status;
+
+enum { EBIC_ROW_MAJOR = 0, EBIC_COL_MAJOR = 1 };
+
+/* Evaluation strategies (ebic_set_path).  Both give identical results.
+ *   DIRECT: every (candidate, row) pair reads the row's values along the
+ *           series from the column-major matrix.
+ *   INDEX:  a per-context pairwise order index, built once on the device,
+ *           holds for every ordered column pair (p, q) the 64-row bitmasks
+ *           of rows with a[r,p] < a[r,q]; evaluation then combines one
+ *           64-bit word per consecutive pair and 64 rows.  Uses
+ *           n_cols^2 * ceil(n_rows/64) * 8 bytes of device memory and
+ *           supports max_violations <= 3 (larger tolerances use DIRECT).
+ *   AUTO:   INDEX when it fits the context's index budget, else DIRECT. */
+enum { EBIC_PATH_AUTO = 0, EBIC_PATH_DIRECT = 1, EBIC_PATH_INDEX = 2 };
+
+/* Trend and fitness parameters of one evaluation. */
+typedef struct {
+    uint32_t struct_size;     /* sizeof(ebic_params) */
+    int32_t sigma;            /* Eq. (1): expected minimal number of rows, >= 0 */
+    int32_t max_violations;   /* k >= 0: consecutive pairs a row may break per
+                                 direction (approximate trends, Step 7) */
+    int32_t negative_trends;  /* 0/1: also accept rows falling along the series
+                                 (negative trends, Step 7); a row is counted
+                                 once if either direction accepts it */
+    int32_t want_masks;       /* 0: counts and fitness only; 1: also row masks */
+} ebic_params;
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(ebic_ctx_info) */
+    int32_t device;
+    int64_t n_rows;
+    int32_t n_cols;
+    int64_t rows_padded;      /* leading dimension of the device matrix */
+    int64_t mask_words;       /* W */
+    int32_t path;             /* requested path (EBIC_PATH_*) */
+    int32_t index_built;      /* 1 once the pairwise order index exists */
+    int64_t index_bytes;      /* size of the index (built or prospective) */
+    int64_t index_budget;     /* AUTO builds the index only within this many bytes */
+    double index_build_ms;    /* device time of the last index build */
+} ebic_ctx_info;
+
+/*
+ * Matrix ingest (Step 1: the data is sent to the GPU once).
+ *
+ * ebic_create copies the host matrix a (n_rows x n_cols, element (r, j) at
+ * a[r*ld + j] for EBIC_ROW_MAJOR or a[j*ld + r] for EBIC_COL_MAJOR) to the
+ * device `device` as a column-major FP32 matrix padded to a multiple of 64
+ * rows, and builds the log table of Eq. (1) on the host.  The caller may
+ * free `a` on return.  ebic_create_device does the same from a device
+ * pointer on that device: it synchronises the device first, so writes to
+ * d_a pending on any stream are seen, and the caller keeps ownership.  The
+ * context owns every device buffer and one HIP stream.
+ * Errors: E_ARG (null pointer, n_rows < 1, n_cols < 1, ld too small, bad
+ * layout), E_NOMEM, E_DEVICE.
+ */
+ebic_status ebic_create(const float *a, int64_t n_rows, int32_t n_cols, int64_t ld,
+                        int32_t layout, int32_t device, ebic_ctx **out);
+ebic_status ebic_create_device(const float *d_a, int64_t n_rows, int32_t n_cols, int64_t ld,
+                               int32_t layout, int32_t device, ebic_ctx **out);
+ebic_status ebic_destroy(ebic_ctx *ctx);
+
+/* W = ceil(n_rows / 64), the number of 64-bit words of one row mask. */
+int64_t ebic_mask_words(int64_t n_rows);
+
+/* Choose the evaluation path (EBIC_PATH_*).  INDEX builds the index now if
+ * it is missing (E_NOMEM if it cannot be allocated).  AUTO defers the
+ * decision to each evaluation. */
+ebic_status ebic_set_path(ebic_ctx *ctx, int32_t path);
+/* Bytes the index may take under AUTO (default: 8 GiB, capped at a quarter
+ * of the device's free memory at creation). */
+ebic_status ebic_set_index_budget(ebic_ctx *ctx, int64_t bytes);
+ebic_status ebic_get_info(const ebic_ctx *ctx, ebic_ctx_info *info);
+
+/*
+ * Population evaluation -- Step 4 (counts and fitness, Eq. (1)) and, with
+ * want_masks, Step 6 (the rows matching each series).
+ *
+ * For each candidate c = (j_0 .. j_{L-1}) and each row r:
+ *   vu = #{t < L-1 : !(a[r,j_t] < a[r,j_{t+1}])}
+ *   vd = #{t < L-1 : !(a[r,j_t] > a[r,j_{t+1}])}
+ *   rising(r)  = vu <= k,  falling(r) = negative_trends && vd <= k
+ *   count[c]   = #{r : rising(r) || falling(r)}
+ *   fitness[c] = count <= 1 ? 0 : 2^min(count - sigma, 0) * L * ln(count - 1)
+ * computed in FP64 with the natural log (Eq. (1); |J| = L).
+ *
+ * ebic_evaluate: host pointers, blocking.  The CBF is validated (E_ARG for
+ * offsets[0] != 0, non-increasing offsets, duplicate columns within a
+ * candidate; E_RANGE for a column outside [0, n_cols), sigma < 0 or k < 0).
+ * masks may be NULL unless want_masks; counts and fitness must not be NULL.
+ * P = 0 returns EBIC_OK and touches nothing.
+ */
+ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
+                          const ebic_params *params, uint64_t *masks, int32_t *counts,
+                          double *fitness);
+
+/*
+ * ebic_evaluate_device: device pointers, ordered on `hip_stream` (a
+ * hipStream_t; NULL = the context's own stream), returns without waiting.
+ * d_offsets holds P+1 int32, d_cols n_entries int32; d_counts P int32,
+ * d_fitness P doubles, d_masks 2*P*W words when want_masks.  The CBF is not
+ * validated on the host: the kernels never read outside [0, n_entries) of
+ * d_cols or outside the matrix, and a candidate whose offsets or columns are
+ * malformed gets count -1 and fitness NaN (its mask words are unspecified).
+ * Calls on one context share its scratch buffers: calls issued on different
+ * streams must not overlap in time.  Duplicate columns are evaluated
+ * by the definition above.  Buffers must stay alive until the stream
+ * reaches the end of the call's work.
+ */
+ebic_status ebic_evaluate_device(ebic_ctx *ctx, const int32_t *d_offsets, const int32_t *d_cols,
+                                 int32_t P, int64_t n_entries, const ebic_params *params,
+                                 uint64_t *d_masks, int32_t *d_counts, double *d_fitness,
+                                 void *hip_stream);
+
+/* Wait for all work on the context's stream. */
+ebic_status ebic_synchronize(ebic_ctx *ctx);
+
+/*
+ * The evolutionary run, Steps 1-7.  The paper fixes the structure; the
+ * constants and operator details below are this library's readings:
+ *
+ *   RNG          SplitMix64 seeded with `seed`; uint(n) = next() % n.
+ *   Step 1       P series of length len_min + uint(len_max - len_min + 1),
+ *                distinct columns by rejection in draw order, a repeated
+ *                series redrawn whole; evaluate; seed the top-rank list.
+ *   Step 2       per-column penalties reset to 0; the first
+ *                min(|top|, floor(P*elite_num/elite_den)) top-rank entries
+ *                join the new population with their scores, adding 1 to
+ *                the penalty of each of their columns.
+ *   Step 3       until P members: tournament of `tournament` draws with
+ *                replacement, adjusted quality fitness / penalty_base^theta,
+ *                theta = (sum of the series' column penalties) / L, first
+ *                best draw wins ties; one operation chosen with weights
+ *                op_weight = {insert, delete, swap, substitute, crossover}
+ *                (crossover takes a second tournament winner); a child seen
+ *                before is a tabu hit, and more than tabu_limit hits (-1: P)
+ *                in one generation end the run (go to Step 6); a novel child
+ *                joins the population and the tabu list and adds 1 to its
+ *                columns' penalties.
+ *   Step 4       the new members are evaluated on the GPU with `eval`.
+ *   Step 5       members by decreasing fitness (ties by position), fitness
+ *                > 0 and not yet listed, are admitted unless a listed entry
+ *                of at least equal fitness overlaps them by more than
+ *                `overlap` (|x & e| / min(|x|, |e|) on column sets); an
+ *                admitted member evicts weaker entries it overlaps by more
+ *                than `overlap`; the list is sorted by fitness (stable) and
+ *                cut to toplist_size.
+ *   Steps 6-7    the listed series are evaluated with `expand` and returned
+ *                with their matching rows (rising | falling).
+ *   Mutations    (Fig. 1a-d) are no-ops when inapplicable and then draw
+ *                nothing: insert needs L < len_max (position uint(L+1), a
+ *                new column by rejection), delete needs L > len_min
+ *                (position uint(L)), swap needs L >= 2 (i = uint(L),
+ *                j = uint(L-1), j += 1 if j >= i), substitute needs
+ *                L < n_cols (position uint(L), a new column by rejection).
+ *   Crossover    (Fig. 1e) i = 1 + uint(|a|), j = uint(|b|), child = a[:i]
+ *                then the columns of b[j:] not in a[:i], cut to len_max; a
+ *                child shorter than len_min is a.
+ *
+ * Generation 0 is Step 1; `generations` more are run unless the tabu rule
+ * stops the run earlier.  on_generation (may be NULL) sees every evaluated
+ * population in CBF with its counts and fitness (elites carry their stored
+ * scores).  Errors: E_ARG for bad bounds (1 <= len_min <= len_max <= n_cols,
+ * P >= 1, tournament >= 1, weights >= 0 with a positive sum, 1 <= elite_den,
+ * 0 <= elite_num <= elite_den, toplist_size >= 1, 0 <= overlap <= 1,
+ * penalty_base > 0) or when P exceeds the number of distinct series.
+ */
+typedef void (*ebic_generation_fn)(void *user, int32_t gen, const int32_t *offsets,
+                                   const int32_t *cols, int32_t P, const int32_t *counts,
+                                   const double *fitness);
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ebic_evolve_params) */
+    int32_t population;         /* P */
+    int32_t len_min, len_max;   /* series length bounds */
+    int32_t tournament;         /* tournament size */
+    int32_t op_weight[5];       /* insert, delete, swap, substitute, crossover */
+    int32_t elite_num, elite_den;  /* elite share of P (Step 2: 1/4) */
+    double penalty_base;        /* crowding penalty base (1.2) */
+    double overlap;             /* top-rank overlap threshold (0.5 or 0.75) */
+    int32_t toplist_size;       /* number of biclusters kept and reported */
+    int32_t tabu_limit;         /* -1: the population size */
+    ebic_params eval;           /* evolution-time trend parameters */
+    ebic_params expand;         /* Step 7 trend parameters */
+    ebic_generation_fn on_generation;
+    void *user;
+} ebic_evolve_params;
+
+/* Fill p with this library's defaults for population P and length bounds. */
+void ebic_evolve_defaults(ebic_evolve_params *p, int32_t population, int32_t len_min,
+                          int32_t len_max, int32_t sigma);
+
+ebic_status ebic_evolve(ebic_ctx *ctx, uint64_t seed, int32_t generations,
+                        const ebic_evolve_params *params, ebic_result **out);
+
+/*
+ * The same run with a caller-supplied evaluator in place of the GPU, for
+ * callers that score candidates themselves (and to test the host steps in
+ * isolation).  eval receives host CBF arrays and must fill counts and
+ * fitness (and masks, W = ebic_mask_words(n_rows) words per direction, when
+ * p->want_masks) and return EBIC_OK.
+ */
+typedef ebic_status (*ebic_eval_fn)(void *user, const int32_t *offsets, const int32_t *cols,
+                                    int32_t P, const ebic_params *p, uint64_t *masks,
+                                    int32_t *counts, double *fitness);
+ebic_status ebic_evolve_with(ebic_eval_fn eval, void *eval_user, int64_t n_rows, int32_t n_cols,
+                             uint64_t seed, int32_t generations,
+                             const ebic_evolve_params *params, ebic_result **out);
+
+/* Result of a run: the top-rank biclusters after Step 7, best first. */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ebic_run_stats) */
+    int32_t generations_run;    /* generations completed after Step 1 */
+    int32_t stopped_by_tabu;    /* 1 if the tabu-hit rule ended the run */
+    int64_t candidates_evaluated;
+    double wall_ms;             /* whole run */
+    double eval_ms;             /* inside Step 4 / Step 6 evaluations */
+    double host_ms;             /* Steps 1-3 and 5 on the host */
+} ebic_run_stats;
+
+int32_t ebic_result_size(const ebic_result *r);
+ebic_status ebic_result_get(const ebic_result *r, int32_t i, const int32_t **cols, int32_t *len,
+                            int32_t *count, double *fitness, const uint64_t **row_mask);
+ebic_status ebic_result_stats(const ebic_result *r, ebic_run_stats *stats);
+void ebic_result_free(ebic_result *r);
+
+/* Message of the last error on ctx (thread-local message when ctx is NULL). */
+const char *ebic_last_error(const ebic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBIC_H */

@@ -1,0 +1,237 @@
+"""ctypes binding of libebic (include/ebic.h).
+
+Argument marshalling only: every step of an evaluation runs in the HIP
+kernels of ``libebic.so``.  There is no CPU fallback -- importing this module
+without the built library raises ``ImportError``.
+
+PyTorch is used only for device memory and streams: the ``*_device`` calls
+take CUDA/HIP tensors and launch on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libebic.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libebic.so is not built ({LIB_PATH}); run "
+                      "`python -m paper_1801_03039_amd.build` (or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- ABI types --
+
+EBIC_OK, EBIC_E_ARG, EBIC_E_RANGE, EBIC_E_NOMEM, EBIC_E_DEVICE, EBIC_E_STATE = range(6)
+EBIC_ROW_MAJOR, EBIC_COL_MAJOR = 0, 1
+EBIC_PATH_AUTO, EBIC_PATH_DIRECT, EBIC_PATH_INDEX = 0, 1, 2
+PATHS = {"auto": EBIC_PATH_AUTO, "direct": EBIC_PATH_DIRECT, "index": EBIC_PATH_INDEX}
+
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_RANGE", 3: "E_NOMEM", 4: "E_DEVICE", 5: "E_STATE"}
+
+_i32, _i64, _u32, _u64, _vp, _dbl = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("sigma", _i32), ("max_violations", _i32),
+                ("negative_trends", _i32), ("want_masks", _i32)]
+
+
+class CtxInfo(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("device", _i32), ("n_rows", _i64), ("n_cols", _i32),
+                ("rows_padded", _i64), ("mask_words", _i64), ("path", _i32),
+                ("index_built", _i32), ("index_bytes", _i64), ("index_budget", _i64),
+                ("index_build_ms", _dbl)]
+
+
+GENERATION_FN = ctypes.CFUNCTYPE(None, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                 _i32, ctypes.POINTER(_i32), ctypes.POINTER(_dbl))
+EVAL_FN = ctypes.CFUNCTYPE(_i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32,
+                           ctypes.POINTER(Params), ctypes.POINTER(_u64), ctypes.POINTER(_i32),
+                           ctypes.POINTER(_dbl))
+
+
+class EvolveParamsC(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("population", _i32), ("len_min", _i32),
+                ("len_max", _i32), ("tournament", _i32), ("op_weight", _i32 * 5),
+                ("elite_num", _i32), ("elite_den", _i32), ("penalty_base", _dbl),
+                ("overlap", _dbl), ("toplist_size", _i32), ("tabu_limit", _i32),
+                ("eval", Params), ("expand", Params), ("on_generation", GENERATION_FN),
+                ("user", _vp)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("generations_run", _i32), ("stopped_by_tabu", _i32),
+                ("candidates_evaluated", _i64), ("wall_ms", _dbl), ("eval_ms", _dbl),
+                ("host_ms", _dbl)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_P = ctypes.POINTER
+_create = _sig("ebic_create", _i32, [_vp, _i64, _i32, _i64, _i32, _i32, _P(_vp)])
+_create_device = _sig("ebic_create_device", _i32, [_vp, _i64, _i32, _i64, _i32, _i32, _P(_vp)])
+_destroy = _sig("ebic_destroy", _i32, [_vp])
+_mask_words = _sig("ebic_mask_words", _i64, [_i64])
+_set_path = _sig("ebic_set_path", _i32, [_vp, _i32])
+_set_budget = _sig("ebic_set_index_budget", _i32, [_vp, _i64])
+_get_info = _sig("ebic_get_info", _i32, [_vp, _P(CtxInfo)])
+_evaluate = _sig("ebic_evaluate", _i32, [_vp, _vp, _vp, _i32, _P(Params), _vp, _vp, _vp])
+_evaluate_device = _sig("ebic_evaluate_device", _i32,
+                        [_vp, _vp, _vp, _i32, _i64, _P(Params), _vp, _vp, _vp, _vp])
+_synchronize = _sig("ebic_synchronize", _i32, [_vp])
+_last_error = _sig("ebic_last_error", ctypes.c_char_p, [_vp])
+
+EXPORTED = ["ebic_create", "ebic_create_device", "ebic_destroy", "ebic_mask_words",
+            "ebic_set_path", "ebic_set_index_budget", "ebic_get_info", "ebic_evaluate",
+            "ebic_evaluate_device", "ebic_synchronize", "ebic_last_error"]
+
+
+class EbicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st: int, ctx=None):
+    if st != EBIC_OK:
+        raise EbicError(st, _last_error(ctx).decode(errors="replace"))
+
+
+def mask_words(n_rows: int) -> int:
+    return int(_mask_words(int(n_rows)))
+
+
+def make_params(sigma: int, max_violations: int = 0, negative_trends: bool = False,
+                want_masks: bool = False) -> Params:
+    return Params(ctypes.sizeof(Params), int(sigma), int(max_violations),
+                  int(bool(negative_trends)), int(bool(want_masks)))
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_vp)
+
+
+class Context:
+    """A matrix resident on one GPU (``ebic_create``)."""
+
+    def __init__(self, a, device: int = 0, path: str = "auto"):
+        h = _vp()
+        if hasattr(a, "is_cuda") and a.is_cuda:
+            t = a.contiguous()
+            if t.dtype.itemsize != 4 or not t.dtype.is_floating_point:
+                raise TypeError("matrix must be float32")
+            n, m = t.shape
+            _check(_create_device(_vp(t.data_ptr()), n, m, m, EBIC_ROW_MAJOR,
+                                  int(t.device.index or 0), ctypes.byref(h)))
+        else:
+            arr = np.ascontiguousarray(a, dtype=np.float32)
+            n, m = arr.shape
+            _check(_create(_np_ptr(arr), n, m, m, EBIC_ROW_MAJOR, int(device), ctypes.byref(h)))
+        self._h = h
+        self.n_rows, self.n_cols = int(n), int(m)
+        self.W = mask_words(self.n_rows)
+        if path != "auto":
+            self.set_path(path)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise EbicError(EBIC_E_STATE, "context is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_path(self, path: str):
+        _check(_set_path(self.handle, PATHS[path]), self.handle)
+
+    def set_index_budget(self, nbytes: int):
+        _check(_set_budget(self.handle, int(nbytes)), self.handle)
+
+    def info(self) -> dict:
+        inf = CtxInfo()
+        inf.struct_size = ctypes.sizeof(CtxInfo)
+        _check(_get_info(self.handle, ctypes.byref(inf)), self.handle)
+        return {f: getattr(inf, f) for f, _ in CtxInfo._fields_ if f != "struct_size"}
+
+    def synchronize(self):
+        _check(_synchronize(self.handle), self.handle)
+
+    # -- host arrays ------------------------------------------------------------
+    def evaluate(self, offsets, cols, *, sigma: int, max_violations: int = 0,
+                 negative_trends: bool = False, want_masks: bool = False) -> dict:
+        """Blocking evaluation of a CBF population given as host arrays."""
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        cl = np.ascontiguousarray(cols, dtype=np.int32)
+        P = len(off) - 1
+        counts = np.zeros(P, dtype=np.int32)
+        fit = np.zeros(P, dtype=np.float64)
+        masks = np.zeros((P, 2, self.W), dtype=np.uint64) if want_masks else None
+        prm = make_params(sigma, max_violations, negative_trends, want_masks)
+        if cl.size == 0:
+            cl = np.zeros(1, dtype=np.int32)
+        _check(_evaluate(self.handle, _np_ptr(off), _np_ptr(cl), P, ctypes.byref(prm),
+                         _np_ptr(masks), _np_ptr(counts), _np_ptr(fit)), self.handle)
+        out = {"counts": counts, "fitness": fit}
+        if want_masks:
+            out["masks"] = masks
+        return out
+
+    # -- device tensors ---------------------------------------------------------
+    def evaluate_device(self, offsets, cols, counts, fitness, masks=None, *, sigma: int,
+                        max_violations: int = 0, negative_trends: bool = False,
+                        stream=None) -> None:
+        """Stream-ordered evaluation of device tensors (int32 offsets/cols,
+        int32 counts, float64 fitness, optional uint64/int64 masks [P,2,W]).
+        Launches on ``stream`` (default: torch's current stream) and returns
+        without waiting."""
+        import torch
+        P = offsets.numel() - 1
+        for t, name in ((offsets, "offsets"), (cols, "cols"), (counts, "counts"),
+                        (fitness, "fitness")):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        if offsets.dtype != torch.int32 or cols.dtype != torch.int32 or counts.dtype != torch.int32:
+            raise TypeError("offsets, cols and counts must be int32")
+        if fitness.dtype != torch.float64:
+            raise TypeError("fitness must be float64")
+        if counts.numel() < P or fitness.numel() < P:
+            raise ValueError("counts/fitness hold fewer than P entries")
+        want = masks is not None
+        if want and (masks.element_size() != 8 or masks.numel() < 2 * P * self.W
+                     or not masks.is_contiguous()):
+            raise ValueError("masks must be a contiguous 64-bit tensor of 2*P*W words")
+        if stream is None:
+            stream = torch.cuda.current_stream(offsets.device)
+        prm = make_params(sigma, max_violations, negative_trends, want)
+        _check(_evaluate_device(self.handle, _vp(offsets.data_ptr()), _vp(cols.data_ptr()), P,
+                                cols.numel(), ctypes.byref(prm),
+                                _vp(masks.data_ptr()) if want else None,
+                                _vp(counts.data_ptr()), _vp(fitness.data_ptr()),
+                                _vp(stream.cuda_stream)), self.handle)

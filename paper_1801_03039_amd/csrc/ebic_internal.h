@@ -1,0 +1,84 @@
+// Internal declarations shared by the libebic runtime, kernels and evolution
+// engine.  Not part of the public ABI (see include/ebic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ebic.h"
+
+namespace ebic {
+
+// Largest approximate tolerance the pairwise-index evaluator handles; it
+// keeps k+1 saturating bit-sliced violation counters per direction.
+constexpr int kIndexMaxViolations = 3;
+
+// Candidate columns staged in LDS by the direct evaluator; longer series
+// read their tail from global memory.
+constexpr int kDirectLdsCols = 512;
+
+struct DeviceBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Launchers (ebic_kernels.hip).  All are asynchronous on `stream` and return
+// the HIP status of the launch.
+hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int32_t layout,
+                         int64_t npad, float *dst, hipStream_t stream);
+
+hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
+                              int64_t wpad, uint64_t *idx, hipStream_t stream);
+
+struct EvalArgs {
+    const int32_t *offsets;
+    const int32_t *cols;
+    int32_t P;
+    int64_t n_entries;
+    int32_t sigma;
+    int32_t k;
+    int32_t negative;
+    uint64_t *masks;      // nullptr: no masks
+    int32_t *counts;
+    double *fitness;
+    int32_t *acc;         // P zero-initialised accumulators; left zeroed
+    int32_t *flags;       // P validity flags, written every call
+};
+
+hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
+                              const EvalArgs &e, hipStream_t stream);
+
+hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
+                             const EvalArgs &e, hipStream_t stream);
+
+hipError_t launch_finalize(const double *logt, const EvalArgs &e, hipStream_t stream);
+
+}  // namespace ebic
+
+struct ebic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0, npad = 0, W = 0, wpad = 0;
+    int32_t m = 0;
+    float *d_a = nullptr;        // column-major [m][npad]
+    double *d_log = nullptr;     // ln(i), i = 0..n
+    // pairwise order index
+    uint64_t *d_idx = nullptr;
+    int64_t idx_bytes = 0;
+    int64_t idx_budget = 0;
+    bool idx_built = false;
+    double idx_ms = 0.0;
+    int32_t path = EBIC_PATH_AUTO;
+    // per-call scratch
+    int32_t *d_acc = nullptr;
+    int32_t *d_flags = nullptr;
+    int64_t cap_P = 0;
+    // staging for the host-pointer entry point
+    int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr;
+    double *d_fit = nullptr;
+    uint64_t *d_masks = nullptr;
+    int64_t cap_off = 0, cap_cols = 0, cap_out = 0, cap_masks = 0;
+    std::string err;
+};

@@ -1,0 +1,389 @@
+// EBIC population evaluation kernels for gfx950 (CDNA4, wave64).
+//
+// The trend test (Motivation: row k follows the series p, q, r when
+// a_kp < a_kq < a_kr, a strict comparison), its negative and approximate
+// variants (Step 7), the row count |I| (Step 4), the row masks (Step 6) and
+// the fitness of Eq. (1) are all computed here.  Nothing in this file is a
+// dense contraction, so nothing uses MFMA: the work is gathers, compares and
+// bit operations, bound by memory and VALU issue.
+//
+// Layouts
+//   matrix  column-major FP32 a[j*npad + r], npad = 64*ceil(n/64), pad rows 0
+//   index   idx[(p*m + q)*wpad + w]: bit b set when row 64w+b < n has
+//           a[r,p] < a[r,q]; wpad = W rounded up to 8 words (64 bytes)
+//   masks   masks[(c*2 + dir)*W + w], dir 0 rising, dir 1 falling
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "ebic_internal.h"
+
+namespace ebic {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t tail_bits(int64_t n, int64_t w, int64_t W) {
+    if (w < W - 1) return ~0ull;
+    const int rem = (int)(n - (W - 1) * 64);  // 1..64
+    return rem == 64 ? ~0ull : ((1ull << rem) - 1ull);
+}
+
+// ---------------------------------------------------------------- ingest --
+
+// Row-major -> padded column-major through a 64x64 LDS tile.
+__global__ __launch_bounds__(kBlock) void ingest_rows_kernel(const float *__restrict__ src,
+                                                             int64_t n, int32_t m, int64_t ld,
+                                                             int64_t npad, int64_t tiles_r,
+                                                             float *__restrict__ dst) {
+    __shared__ float tile[64][65];
+    const int64_t tr = blockIdx.x % tiles_r;
+    const int64_t tj = blockIdx.x / tiles_r;
+    const int64_t r0 = tr * 64;
+    const int32_t j0 = (int32_t)(tj * 64);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i;
+        const int32_t j = j0 + tx;
+        tile[i][tx] = (r < n && j < m) ? src[r * ld + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int32_t j = j0 + i;
+        if (j < m) dst[(int64_t)j * npad + r0 + tx] = tile[tx][i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void ingest_cols_kernel(const float *__restrict__ src,
+                                                             int64_t n, int32_t m, int64_t ld,
+                                                             int64_t npad,
+                                                             float *__restrict__ dst) {
+    const int64_t total = (int64_t)m * npad;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = i / npad, r = i - j * npad;
+        dst[i] = r < n ? src[j * ld + r] : 0.0f;
+    }
+}
+
+// ----------------------------------------------------------- index build --
+//
+// One wave per (64-row word w, block of kPB columns p).  Lane = row.  The
+// kPB values a[r,p] stay in registers while the wave streams every column q
+// once: each compare is one ballot giving 64 rows of lt(p,q) at once.
+constexpr int kPB = 16;
+
+__global__ __launch_bounds__(kBlock) void index_build_kernel(const float *__restrict__ a,
+                                                             int64_t n, int64_t npad, int32_t m,
+                                                             int64_t W, int64_t wpad,
+                                                             int64_t wblocks,
+                                                             uint64_t *__restrict__ idx) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t wb = blockIdx.x % wblocks;
+    const int32_t p0 = (int32_t)(blockIdx.x / wblocks) * kPB;
+    const int64_t w = wb * 4 + wv;
+    if (w >= W) return;  // uniform per wave
+    const int64_t r = w * 64 + lane;
+    const bool valid = r < n;
+    float vp[kPB];
+#pragma unroll
+    for (int i = 0; i < kPB; ++i) vp[i] = (p0 + i < m) ? a[(int64_t)(p0 + i) * npad + r] : 0.0f;
+    const bool writer = lane < kPB && p0 + lane < m;
+    uint64_t *out = idx + ((int64_t)(p0 + lane) * m) * wpad + w;
+    for (int32_t q = 0; q < m; ++q) {
+        const float vq = a[(int64_t)q * npad + r];
+        uint64_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < kPB; ++i) {
+            const uint64_t bits = ballot(valid && vp[i] < vq);
+            mine = (lane == i) ? bits : mine;
+        }
+        if (writer) out[(int64_t)q * wpad] = mine;
+    }
+}
+
+// ------------------------------------------------------- direct evaluator --
+//
+// Workgroup = (candidate c, row slice s); 4 waves, lane = row.  The
+// candidate's column offsets (col * npad) are staged in LDS once; each wave
+// walks 64-row blocks of its slice, reading the row's values along the
+// series (coalesced 256-byte loads of the column-major matrix), counting
+// violating pairs per lane and leaving the block as soon as every row of the
+// wave is decided.  With 8 slices, slice s runs on XCD s (workgroups are
+// dealt to the 8 XCDs round-robin), so each XCD's L2 holds one eighth of
+// the matrix.
+template <bool NEG>
+__global__ __launch_bounds__(kBlock) void eval_direct_kernel(
+    const float *__restrict__ a, int64_t n, int64_t npad, int32_t m, int64_t W, int32_t S,
+    const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols, int64_t n_entries,
+    int32_t k, uint64_t *__restrict__ masks, int32_t *__restrict__ acc,
+    int32_t *__restrict__ flags) {
+    __shared__ int64_t s_off[kDirectLdsCols];
+    __shared__ int32_t s_bad;
+    __shared__ int32_t s_cnt[kBlock / kWave];
+    const int c = (int)(blockIdx.x / S);
+    const int s = (int)(blockIdx.x % S);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    const int64_t start = offsets[c], end = offsets[c + 1];
+    const bool ok_range = start >= 0 && end <= n_entries && end > start;
+    if (tid == 0) s_bad = ok_range ? 0 : 1;
+    __syncthreads();
+    const int32_t L = ok_range ? (int32_t)(end - start) : 0;
+    for (int32_t t = tid; t < L; t += kBlock) {
+        const int32_t col = cols[start + t];
+        if (col < 0 || col >= m) s_bad = 1;
+        if (t < kDirectLdsCols) s_off[t] = (int64_t)(col < 0 || col >= m ? 0 : col) * npad;
+    }
+    __syncthreads();
+    const bool bad = s_bad != 0;
+    if (s == 0 && tid == 0) flags[c] = bad ? 1 : 0;
+    if (bad) return;  // uniform per workgroup
+
+    const int64_t rb0 = (W * s) / S, rb1 = (W * (s + 1)) / S;
+    int32_t cnt = 0;
+    for (int64_t rb = rb0 + wv; rb < rb1; rb += kBlock / kWave) {
+        const int64_t r = rb * 64 + lane;
+        const bool valid = r < n;
+        const float *base = a + r;
+        float prev = base[s_off[0]];
+        int32_t vu = 0, vd = 0;
+        for (int32_t t0 = 1; t0 < L; t0 += 4) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t t = t0 + u;
+                if (t < L) {
+                    const int64_t off =
+                        t < kDirectLdsCols ? s_off[t] : (int64_t)cols[start + t] * npad;
+                    v[u] = base[off];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u < L) {
+                    vu += !(prev < v[u]);
+                    if (NEG) vd += !(prev > v[u]);
+                    prev = v[u];
+                }
+            }
+            const bool alive = (vu <= k) || (NEG && vd <= k);
+            if (ballot(alive && valid) == 0) break;
+        }
+        const uint64_t bp = ballot(valid && vu <= k);
+        const uint64_t bn = NEG ? ballot(valid && vd <= k) : 0ull;
+        cnt += __popcll(bp | bn);
+        if (masks && lane == 0) {
+            masks[((int64_t)c * 2 + 0) * W + rb] = bp;
+            masks[((int64_t)c * 2 + 1) * W + rb] = bn;
+        }
+    }
+    if (lane == 0) s_cnt[wv] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t sum = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) sum += s_cnt[i];
+        if (sum) atomicAdd(acc + c, sum);
+    }
+}
+
+// -------------------------------------------------------- index evaluator --
+//
+// Thread = (candidate c, 64-row word w), flattened c-major over the grid.
+// Per consecutive pair (p, q) it reads lt(p,q) -- and lt(q,p) for the
+// falling direction -- from the pairwise order index and folds the violation
+// words (complements) into K+1 saturating bit-sliced counters per direction:
+// cnt[i] has bit b set when row b has more than i violations.  A lane stops
+// once every row of its word is rejected in every enabled direction.
+template <int K, bool NEG>
+__global__ __launch_bounds__(kBlock) void eval_index_kernel(
+    const uint64_t *__restrict__ idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
+    const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols, int32_t P,
+    int64_t n_entries, uint64_t *__restrict__ masks, int32_t *__restrict__ acc,
+    int32_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t total = (int64_t)P * W;
+    const bool active = item < total;
+    const int64_t c = active ? item / W : (int64_t)P - 1;
+    const int64_t w = active ? item - c * W : 0;
+
+    const int64_t start = offsets[c], end = offsets[c + 1];
+    const bool ok_range = start >= 0 && end <= n_entries && end > start;
+    const int32_t L = ok_range ? (int32_t)(end - start) : 0;
+
+    // One lane per candidate validates every column and publishes the flag;
+    // other lanes only clamp column indices so that no read leaves the index.
+    if (active && w == 0) {
+        int32_t bad = ok_range ? 0 : 1;
+        for (int32_t t = 0; t < L; ++t) {
+            const int32_t col = cols[start + t];
+            bad |= (col < 0 || col >= m) ? 1 : 0;
+        }
+        flags[c] = bad;
+    }
+
+    const uint64_t valid = (active && ok_range) ? tail_bits(n, w, W) : 0ull;
+    uint64_t cu[K + 1], cd[K + 1];
+#pragma unroll
+    for (int i = 0; i <= K; ++i) cu[i] = cd[i] = 0ull;
+
+    if (valid) {
+        const int32_t *sc = cols + start;
+        int32_t p = sc[0];
+        p = (p < 0 || p >= m) ? 0 : p;
+        for (int32_t t = 1; t < L; ++t) {
+            int32_t q = sc[t];
+            q = (q < 0 || q >= m) ? 0 : q;
+            const uint64_t vu = ~idx[((int64_t)p * m + q) * wpad + w];
+#pragma unroll
+            for (int i = K; i > 0; --i) cu[i] |= cu[i - 1] & vu;
+            cu[0] |= vu;
+            uint64_t dead = cu[K];
+            if (NEG) {
+                const uint64_t vd = ~idx[((int64_t)q * m + p) * wpad + w];
+#pragma unroll
+                for (int i = K; i > 0; --i) cd[i] |= cd[i - 1] & vd;
+                cd[0] |= vd;
+                dead &= cd[K];
+            }
+            p = q;
+            if ((valid & ~dead) == 0ull) break;
+        }
+    }
+    const uint64_t pos = valid & ~cu[K];
+    const uint64_t neg = NEG ? (valid & ~cd[K]) : 0ull;
+    if (masks && active) {
+        masks[(c * 2 + 0) * W + w] = pos;
+        masks[(c * 2 + 1) * W + w] = neg;
+    }
+
+    // Segmented sum over lanes of the same candidate (lanes hold consecutive
+    // items, so each candidate is one contiguous run of lanes), then one
+    // atomic per run.
+    int32_t cnt = __popcll(pos | neg);
+    const int32_t cc = (int32_t)c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t v = __shfl_down(cnt, off);
+        const int32_t oc = __shfl_down(cc, off);
+        if (lane + off < kWave && oc == cc) cnt += v;
+    }
+    const int32_t prev_c = __shfl_up(cc, 1);
+    const bool head = lane == 0 || prev_c != cc;
+    if (active && head && cnt) atomicAdd(acc + c, cnt);
+}
+
+// --------------------------------------------------------------- finalize --
+//
+// counts and Eq. (1).  ln(count-1) comes from a table built on the host with
+// the C library's log; L * ln is one rounded FP64 product and 2^e is an exact
+// scaling, so the result equals the host formula bit for bit.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(int32_t P, int32_t sigma,
+                                                          const int32_t *__restrict__ offsets,
+                                                          const double *__restrict__ logt,
+                                                          int32_t *__restrict__ acc,
+                                                          const int32_t *__restrict__ flags,
+                                                          int32_t *__restrict__ counts,
+                                                          double *__restrict__ fitness) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= P) return;
+    const int32_t cnt = acc[c];
+    acc[c] = 0;
+    if (flags[c]) {
+        counts[c] = -1;
+        fitness[c] = __builtin_nan("");
+        return;
+    }
+    const int32_t L = offsets[c + 1] - offsets[c];
+    counts[c] = cnt;
+    double f = 0.0;
+    if (cnt > 1) {
+        const int32_t e = cnt - sigma < 0 ? cnt - sigma : 0;
+        f = ldexp((double)L * logt[cnt - 1], e);
+    }
+    fitness[c] = f;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launchers --
+
+hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int32_t layout,
+                         int64_t npad, float *dst, hipStream_t stream) {
+    if (layout == EBIC_ROW_MAJOR) {
+        const int64_t tiles_r = npad / 64, tiles_j = (m + 63) / 64;
+        hipLaunchKernelGGL(ingest_rows_kernel, dim3((unsigned)(tiles_r * tiles_j)), dim3(kBlock),
+                           0, stream, src, n, m, ld, npad, tiles_r, dst);
+    } else {
+        const int64_t total = (int64_t)m * npad;
+        int64_t blocks = (total + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(ingest_cols_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
+                           src, n, m, ld, npad, dst);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
+                              int64_t wpad, uint64_t *idx, hipStream_t stream) {
+    const int64_t wblocks = (W + 3) / 4;
+    const int64_t pblocks = (m + kPB - 1) / kPB;
+    hipLaunchKernelGGL(index_build_kernel, dim3((unsigned)(wblocks * pblocks)), dim3(kBlock), 0,
+                       stream, a, n, npad, m, W, wpad, wblocks, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
+                              const EvalArgs &e, hipStream_t stream) {
+    const int32_t S = W >= 32 ? kXcds : 1;
+    const dim3 grid((unsigned)((int64_t)e.P * S));
+    if (e.negative)
+        hipLaunchKernelGGL(eval_direct_kernel<true>, grid, dim3(kBlock), 0, stream, a, n, npad, m,
+                           W, S, e.offsets, e.cols, e.n_entries, e.k, e.masks, e.acc, e.flags);
+    else
+        hipLaunchKernelGGL(eval_direct_kernel<false>, grid, dim3(kBlock), 0, stream, a, n, npad,
+                           m, W, S, e.offsets, e.cols, e.n_entries, e.k, e.masks, e.acc, e.flags);
+    return hipGetLastError();
+}
+
+template <int K>
+static void launch_index_k(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
+                           const EvalArgs &e, hipStream_t stream) {
+    const int64_t total = (int64_t)e.P * W;
+    const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+    if (e.negative)
+        hipLaunchKernelGGL((eval_index_kernel<K, true>), grid, dim3(kBlock), 0, stream, idx, n, m,
+                           W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.masks, e.acc, e.flags);
+    else
+        hipLaunchKernelGGL((eval_index_kernel<K, false>), grid, dim3(kBlock), 0, stream, idx, n,
+                           m, W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.masks, e.acc,
+                           e.flags);
+}
+
+hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
+                             const EvalArgs &e, hipStream_t stream) {
+    switch (e.k) {
+    case 0: launch_index_k<0>(idx, n, m, W, wpad, e, stream); break;
+    case 1: launch_index_k<1>(idx, n, m, W, wpad, e, stream); break;
+    case 2: launch_index_k<2>(idx, n, m, W, wpad, e, stream); break;
+    case 3: launch_index_k<3>(idx, n, m, W, wpad, e, stream); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *logt, const EvalArgs &e, hipStream_t stream) {
+    const dim3 grid((unsigned)((e.P + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(finalize_kernel, grid, dim3(kBlock), 0, stream, e.P, e.sigma, e.offsets,
+                       logt, e.acc, e.flags, e.counts, e.fitness);
+    return hipGetLastError();
+}
+
+}  // namespace ebic
