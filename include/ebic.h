@@ -145,7 +145,7 @@ ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *
 
 /*
  * ebic_evaluate_device: device pointers, ordered on `hip_stream` (a
- * hipStream_t; NULL = the context's own stream), returns without waiting.
+ * hipStream_t; NULL is the HIP null stream), returns without waiting.
  * d_offsets holds P+1 int32, d_cols n_entries int32; d_counts P int32,
  * d_fitness P doubles, d_masks 2*P*W words when want_masks.  The CBF is not
  * validated on the host: the kernels never read outside [0, n_entries) of
@@ -273,7 +273,10 @@ ebic_status ebic_result_get(const ebic_result *r, int32_t i, const int32_t **col
 ebic_status ebic_result_stats(const ebic_result *r, ebic_run_stats *stats);
 void ebic_result_free(ebic_result *r);
 
-/* Message of the last error on ctx (thread-local message when ctx is NULL). */
+/* Message of the last error on ctx.  With ctx == NULL: the calling thread's
+ * last error from a call that had no context (ebic_create*, argument errors
+ * of ebic_evolve*, ebic_result_*); an evaluation failure inside
+ * ebic_evolve is reported on its context. */
 const char *ebic_last_error(const ebic_ctx *ctx);
 
 #ifdef __cplusplus

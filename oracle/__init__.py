@@ -44,7 +44,7 @@ def _load():
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.oracle_evaluate.restype = ctypes.c_int
     lib.oracle_evaluate.argtypes = [p, i64, i32, i64, p, p, i32, i32, i32, i32,
-                                    p, p, p, p, i32]
+                                    p, p, p, p, p, i32]
     lib.oracle_fitness.restype = ctypes.c_double
     lib.oracle_fitness.argtypes = [i64, i64, i64]
     lib.oracle_check_population.restype = ctypes.c_int
@@ -72,13 +72,13 @@ def fitness(count: int, length: int, sigma: int) -> float:
 def evaluate(a: np.ndarray, offsets: np.ndarray, cols: np.ndarray, *, sigma: int,
              max_violations: int = 0, negative_trends: bool = False,
              want_masks: bool = False, want_reads: bool = False,
-             nthreads: int = 0) -> dict:
+             want_depth: bool = False, nthreads: int = 0) -> dict:
     """Evaluate a CBF population on the row-major FP32 matrix ``a``.
 
     Returns ``counts`` (int32[P]), ``fitness`` (float64[P]) and, when asked,
     ``masks`` (uint64[P, 2, W]; dir 0 rising, dir 1 falling) and ``reads``
     (int64[P], the per-candidate sum of values each row must read before its
-    decision is fixed).
+    decision is fixed) and ``depth`` (int32[P, N], that count per row).
     """
     lib = _load()
     a = np.ascontiguousarray(a, dtype=np.float32)
@@ -91,9 +91,11 @@ def evaluate(a: np.ndarray, offsets: np.ndarray, cols: np.ndarray, *, sigma: int
     fit = np.zeros(P, dtype=np.float64)
     masks = np.zeros((P, 2, w), dtype=np.uint64) if want_masks else None
     reads = np.zeros(P, dtype=np.int64) if want_reads else None
+    depth = np.zeros((P, n), dtype=np.int32) if want_depth else None
     st = lib.oracle_evaluate(_ptr(a), n, m, m, _ptr(offsets), _ptr(cols), P,
                              int(sigma), int(max_violations), int(bool(negative_trends)),
-                             _ptr(masks), _ptr(counts), _ptr(fit), _ptr(reads), int(nthreads))
+                             _ptr(masks), _ptr(counts), _ptr(fit), _ptr(reads), _ptr(depth),
+                             int(nthreads))
     if st != 0:
         raise OracleError(st)
     out = {"counts": counts, "fitness": fit}
@@ -101,6 +103,8 @@ def evaluate(a: np.ndarray, offsets: np.ndarray, cols: np.ndarray, *, sigma: int
         out["masks"] = masks
     if want_reads:
         out["reads"] = reads
+    if want_depth:
+        out["depth"] = depth
     return out
 
 

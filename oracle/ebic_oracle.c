@@ -88,13 +88,14 @@ int oracle_check_population(const int32_t *offsets, const int32_t *cols, int32_t
  *                decision is fixed (L if accepted; otherwise 2 + the 0-based
  *                index of the pair after which every enabled direction has
  *                more than k violations)
+ *   depth        NULL, or P*N: d(c,r) itself, at depth[c*N + r]
  *   nthreads     OpenMP threads over candidates (<= 0: runtime default)
  */
 int oracle_evaluate(const float *a, int64_t N, int32_t M, int64_t ld,
                     const int32_t *offsets, const int32_t *cols, int32_t P,
                     int32_t sigma, int32_t k, int32_t negative,
                     uint64_t *masks, int32_t *counts, double *fitness,
-                    int64_t *values_read, int32_t nthreads)
+                    int64_t *values_read, int32_t *depth, int32_t nthreads)
 {
     if (!a || N < 1 || M < 1 || ld < M || !counts || !fitness)
         return ORACLE_E_ARG;
@@ -139,6 +140,8 @@ int oracle_evaluate(const float *a, int64_t N, int32_t M, int64_t ld,
             if (pos || neg)
                 count++;
             read += d;
+            if (depth)
+                depth[(size_t)c * (size_t)N + (size_t)r] = (int32_t)d;
             if (masks) {
                 if (pos)
                     masks[((size_t)c * 2 + 0) * W + (size_t)(r / 64)] |= (uint64_t)1 << (r % 64);

@@ -13,6 +13,12 @@ from .binding import (  # noqa: F401
     EBIC_PATH_DIRECT,
     EBIC_PATH_INDEX,
     LIB_PATH,
+    EvolveConfig,
+    EvolveResult,
+    Generation,
+    Trend,
+    evolve,
+    evolve_with,
     make_params,
     mask_words,
 )

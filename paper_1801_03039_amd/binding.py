@@ -23,6 +23,16 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"libebic.so is not built ({LIB_PATH}); run "
                       "`python -m paper_1801_03039_amd.build` (or __graft_entry__.build())")
 
+# PyTorch-ROCm ships its own HIP runtime under the same SONAME
+# (libamdhip64.so.7) as /opt/rocm's.  Loading torch first makes the dynamic
+# loader bind libebic to torch's already-loaded runtime, so the process holds
+# one HIP/HSA runtime and torch's device pointers and streams are valid for
+# libebic.  Loading libebic first would bring in a second runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:  # CPU-only use (argument checks, ebic_evolve_with)
+    torch = None
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- ABI types --
@@ -211,6 +221,15 @@ class Context:
         int32 counts, float64 fitness, optional uint64/int64 masks [P,2,W]).
         Launches on ``stream`` (default: torch's current stream) and returns
         without waiting."""
+        self.device_call(offsets, cols, counts, fitness, masks, sigma=sigma,
+                         max_violations=max_violations, negative_trends=negative_trends,
+                         stream=stream)()
+
+    def device_call(self, offsets, cols, counts, fitness, masks=None, *, sigma: int,
+                    max_violations: int = 0, negative_trends: bool = False, stream=None):
+        """Validate the tensors once and return a no-argument callable that
+        launches ``ebic_evaluate_device`` on them (the tensors must stay
+        alive and keep their storage while the callable is used)."""
         import torch
         P = offsets.numel() - 1
         for t, name in ((offsets, "offsets"), (cols, "cols"), (counts, "counts"),
@@ -230,8 +249,192 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(offsets.device)
         prm = make_params(sigma, max_violations, negative_trends, want)
-        _check(_evaluate_device(self.handle, _vp(offsets.data_ptr()), _vp(cols.data_ptr()), P,
-                                cols.numel(), ctypes.byref(prm),
-                                _vp(masks.data_ptr()) if want else None,
-                                _vp(counts.data_ptr()), _vp(fitness.data_ptr()),
-                                _vp(stream.cuda_stream)), self.handle)
+        h = self.handle
+        args = (h, _vp(offsets.data_ptr()), _vp(cols.data_ptr()), P, cols.numel(),
+                ctypes.byref(prm), _vp(masks.data_ptr()) if want else None,
+                _vp(counts.data_ptr()), _vp(fitness.data_ptr()), _vp(stream.cuda_stream))
+        fn = _evaluate_device
+
+        def call():
+            st = fn(*args)
+            if st != EBIC_OK:
+                _check(st, h)
+        call.params = prm          # keep the struct alive with the callable
+        return call
+
+
+# ------------------------------------------------------------------ evolution --
+
+_evolve = _sig("ebic_evolve", _i32, [_vp, _u64, _i32, _P(EvolveParamsC), _P(_vp)])
+_evolve_with = _sig("ebic_evolve_with", _i32,
+                    [EVAL_FN, _vp, _i64, _i32, _u64, _i32, _P(EvolveParamsC), _P(_vp)])
+_evolve_defaults = _sig("ebic_evolve_defaults", None, [_P(EvolveParamsC), _i32, _i32, _i32, _i32])
+_result_size = _sig("ebic_result_size", _i32, [_vp])
+_result_get = _sig("ebic_result_get", _i32,
+                   [_vp, _i32, _P(_P(_i32)), _P(_i32), _P(_i32), _P(_dbl), _P(_P(_u64))])
+_result_stats = _sig("ebic_result_stats", _i32, [_vp, _P(RunStats)])
+_result_free = _sig("ebic_result_free", None, [_vp])
+
+EXPORTED += ["ebic_evolve", "ebic_evolve_with", "ebic_evolve_defaults", "ebic_result_size",
+             "ebic_result_get", "ebic_result_stats", "ebic_result_free"]
+
+
+@dataclass
+class Trend:
+    """Trend and fitness parameters (sigma of Eq. (1), tolerance k, negative trends)."""
+    sigma: int
+    max_violations: int = 0
+    negative_trends: bool = False
+
+
+@dataclass
+class EvolveConfig:
+    population: int
+    len_min: int
+    len_max: int
+    eval: Trend
+    expand: Trend
+    tournament: int = 3
+    op_weight: Tuple[int, int, int, int, int] = (1, 1, 1, 1, 1)
+    elite_num: int = 1
+    elite_den: int = 4
+    penalty_base: float = 1.2
+    overlap: float = 0.5
+    toplist_size: int = 100
+    tabu_limit: int = -1
+
+
+@dataclass
+class Generation:
+    gen: int
+    offsets: np.ndarray
+    cols: np.ndarray
+    counts: np.ndarray
+    fitness: np.ndarray
+
+    @property
+    def population(self) -> List[tuple]:
+        o, c = self.offsets, self.cols
+        return [tuple(int(x) for x in c[o[i]:o[i + 1]]) for i in range(len(o) - 1)]
+
+
+@dataclass
+class EvolveResult:
+    biclusters: List[dict]
+    stats: dict
+
+
+def _trend_c(t: Trend, want_masks: bool) -> Params:
+    return make_params(t.sigma, t.max_violations, t.negative_trends, want_masks)
+
+
+def _params_c(cfg: EvolveConfig, on_gen) -> EvolveParamsC:
+    p = EvolveParamsC()
+    p.struct_size = ctypes.sizeof(EvolveParamsC)
+    p.population, p.len_min, p.len_max = cfg.population, cfg.len_min, cfg.len_max
+    p.tournament = cfg.tournament
+    for i, w in enumerate(cfg.op_weight):
+        p.op_weight[i] = int(w)
+    p.elite_num, p.elite_den = cfg.elite_num, cfg.elite_den
+    p.penalty_base, p.overlap = float(cfg.penalty_base), float(cfg.overlap)
+    p.toplist_size, p.tabu_limit = cfg.toplist_size, cfg.tabu_limit
+    p.eval = _trend_c(cfg.eval, False)
+    p.expand = _trend_c(cfg.expand, True)
+    p.on_generation = on_gen
+    p.user = None
+    return p
+
+
+def _gen_callback(fn: Optional[Callable[[Generation], None]]):
+    if fn is None:
+        return GENERATION_FN()
+
+    def cb(user, gen, off, cols, P, counts, fit):
+        o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
+        n = int(o[-1])
+        c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+        fn(Generation(int(gen), o, c, np.ctypeslib.as_array(counts, shape=(P,)).copy(),
+                      np.ctypeslib.as_array(fit, shape=(P,)).copy()))
+    return GENERATION_FN(cb)
+
+
+def _collect(res_ptr) -> EvolveResult:
+    try:
+        out = []
+        for i in range(_result_size(res_ptr)):
+            cols, L, cnt, fit, mask = _P(_i32)(), _i32(), _i32(), _dbl(), _P(_u64)()
+            _check(_result_get(res_ptr, i, ctypes.byref(cols), ctypes.byref(L), ctypes.byref(cnt),
+                               ctypes.byref(fit), ctypes.byref(mask)))
+            out.append({"cols": tuple(int(x) for x in cols[:L.value]), "count": cnt.value,
+                        "fitness": fit.value, "mask_ptr": mask})
+        st = RunStats()
+        st.struct_size = ctypes.sizeof(RunStats)
+        _check(_result_stats(res_ptr, ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in RunStats._fields_ if f != "struct_size"}
+        return EvolveResult(out, stats)
+    except Exception:
+        _result_free(res_ptr)
+        raise
+
+
+def _finish(res_ptr, n_rows: int) -> EvolveResult:
+    r = _collect(res_ptr)
+    W = mask_words(n_rows)
+    for b in r.biclusters:
+        b["mask_words"] = np.ctypeslib.as_array(b.pop("mask_ptr"), shape=(W,)).copy()
+    _result_free(res_ptr)
+    return r
+
+
+def evolve(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
+           on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
+    """EBIC run (Steps 1-7) on the GPU context ``ctx``."""
+    cb = _gen_callback(on_generation)
+    p = _params_c(cfg, cb)
+    res = _vp()
+    st = _evolve(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations), ctypes.byref(p),
+                 ctypes.byref(res))
+    if st != EBIC_OK:
+        msg = _last_error(ctx.handle).decode(errors="replace") or _last_error(None).decode(errors="replace")
+        raise EbicError(st, msg)
+    return _finish(res, ctx.n_rows)
+
+
+def evolve_with(evaluate: Callable, n_rows: int, n_cols: int, seed: int, generations: int,
+                cfg: EvolveConfig,
+                on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
+    """The same run with a Python evaluator in place of the GPU.
+
+    ``evaluate(offsets, cols, sigma, max_violations, negative_trends,
+    want_masks)`` returns (counts, fitness, masks-or-None) as NumPy arrays;
+    masks are uint64 [P, 2, W]."""
+    W = mask_words(n_rows)
+    errors = []
+
+    def cb(user, off, cols, P, prm, masks, counts, fit):
+        try:
+            o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
+            n = int(o[-1])
+            c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+            pr = prm.contents
+            cnt, f, m = evaluate(o, c, pr.sigma, pr.max_violations, bool(pr.negative_trends),
+                                 bool(pr.want_masks))
+            np.ctypeslib.as_array(counts, shape=(P,))[:] = cnt
+            np.ctypeslib.as_array(fit, shape=(P,))[:] = f
+            if pr.want_masks:
+                np.ctypeslib.as_array(masks, shape=(P * 2 * W,))[:] = np.asarray(m, dtype=np.uint64).ravel()
+            return EBIC_OK
+        except Exception as ex:  # reported after the run
+            errors.append(ex)
+            return EBIC_E_DEVICE
+
+    efn = EVAL_FN(cb)
+    gcb = _gen_callback(on_generation)
+    p = _params_c(cfg, gcb)
+    res = _vp()
+    st = _evolve_with(efn, None, int(n_rows), int(n_cols), int(seed) & ((1 << 64) - 1),
+                      int(generations), ctypes.byref(p), ctypes.byref(res))
+    if errors:
+        raise errors[0]
+    _check(st)
+    return _finish(res, n_rows)

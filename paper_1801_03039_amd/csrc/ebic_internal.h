@@ -43,8 +43,8 @@ struct EvalArgs {
     uint64_t *masks;      // nullptr: no masks
     int32_t *counts;
     double *fitness;
-    int32_t *acc;         // P zero-initialised accumulators; left zeroed
-    int32_t *flags;       // P validity flags, written every call
+    const double *logt;          // ln(i), i = 0..n
+    unsigned long long *acc;     // P zero-initialised packed accumulators; left zeroed
 };
 
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
@@ -52,8 +52,6 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
 
 hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
                              const EvalArgs &e, hipStream_t stream);
-
-hipError_t launch_finalize(const double *logt, const EvalArgs &e, hipStream_t stream);
 
 }  // namespace ebic
 
@@ -72,8 +70,7 @@ struct ebic_ctx {
     double idx_ms = 0.0;
     int32_t path = EBIC_PATH_AUTO;
     // per-call scratch
-    int32_t *d_acc = nullptr;
-    int32_t *d_flags = nullptr;
+    unsigned long long *d_acc = nullptr;
     int64_t cap_P = 0;
     // staging for the host-pointer entry point
     int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr;

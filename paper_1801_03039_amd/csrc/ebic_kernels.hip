@@ -12,6 +12,9 @@
 //   index   idx[(p*m + q)*wpad + w]: bit b set when row 64w+b < n has
 //           a[r,p] < a[r,q]; wpad = W rounded up to 8 words (64 bytes)
 //   masks   masks[(c*2 + dir)*W + w], dir 0 rising, dir 1 falling
+//
+// One evaluation is one kernel launch: the part of each candidate that
+// finishes last writes its count and fitness.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -108,6 +111,49 @@ __global__ __launch_bounds__(kBlock) void index_build_kernel(const float *__rest
     }
 }
 
+// --------------------------------------------------------- fitness (Eq. 1) --
+//
+// Each part of a candidate (a workgroup's row slice, or a run of 64-row
+// words) reports with ONE 64-bit atomic add on acc[c]:
+//   bits  0..31  rows it accepted (|I| <= n < 2^31)
+//   bit  32      set by the part that found the candidate malformed
+//   bits 33..63  its share of the candidate's `parts`
+// The part whose add completes the shares owns the total: a single
+// read-modify-write orders everything, so no memory fence is needed.  It
+// resets acc[c] for the next call and writes the count and Eq. (1).
+// ln(count-1) comes from a table built on the host with the C library's
+// log; L * ln is one rounded FP64 product and 2^e an exact scaling, so the
+// result equals the host formula bit for bit.
+constexpr int kShareShift = 33;
+constexpr uint64_t kBadBit = 1ull << 32;
+
+__device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, int64_t share,
+                                            int64_t parts, int32_t L, int32_t sigma,
+                                            const double *__restrict__ logt,
+                                            unsigned long long *__restrict__ acc,
+                                            int32_t *__restrict__ counts,
+                                            double *__restrict__ fitness) {
+    const unsigned long long add =
+        ((unsigned long long)share << kShareShift) | (bad ? kBadBit : 0ull) | cnt;
+    const unsigned long long before = atomicAdd(acc + c, add);
+    const unsigned long long now = before + add;
+    if ((int64_t)(now >> kShareShift) != parts) return;
+    atomicExch(acc + c, 0ull);
+    if (now & kBadBit) {
+        counts[c] = -1;
+        fitness[c] = __builtin_nan("");
+        return;
+    }
+    const int32_t total = (int32_t)(uint32_t)now;
+    counts[c] = total;
+    double f = 0.0;
+    if (total > 1) {
+        const int32_t e = total - sigma < 0 ? total - sigma : 0;
+        f = ldexp((double)L * logt[total - 1], e);
+    }
+    fitness[c] = f;
+}
+
 // ------------------------------------------------------- direct evaluator --
 //
 // Workgroup = (candidate c, row slice s); 4 waves, lane = row.  The
@@ -122,8 +168,9 @@ template <bool NEG>
 __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
     const float *__restrict__ a, int64_t n, int64_t npad, int32_t m, int64_t W, int32_t S,
     const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols, int64_t n_entries,
-    int32_t k, uint64_t *__restrict__ masks, int32_t *__restrict__ acc,
-    int32_t *__restrict__ flags) {
+    int32_t k, int32_t sigma, const double *__restrict__ logt, uint64_t *__restrict__ masks,
+    unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
+    double *__restrict__ fitness) {
     __shared__ int64_t s_off[kDirectLdsCols];
     __shared__ int32_t s_bad;
     __shared__ int32_t s_cnt[kBlock / kWave];
@@ -143,8 +190,13 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
     }
     __syncthreads();
     const bool bad = s_bad != 0;
-    if (s == 0 && tid == 0) flags[c] = bad ? 1 : 0;
-    if (bad) return;  // uniform per workgroup
+    if (bad) {  // uniform per workgroup
+        if (s == 0 && tid == 0) {
+            counts[c] = -1;
+            fitness[c] = __builtin_nan("");
+        }
+        return;
+    }
 
     const int64_t rb0 = (W * s) / S, rb1 = (W * (s + 1)) / S;
     int32_t cnt = 0;
@@ -189,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
     if (tid == 0) {
         int32_t sum = 0;
         for (int i = 0; i < kBlock / kWave; ++i) sum += s_cnt[i];
-        if (sum) atomicAdd(acc + c, sum);
+        finish_part(c, (uint32_t)sum, false, 1, S, L, sigma, logt, acc, counts, fitness);
     }
 }
 
@@ -205,8 +257,9 @@ template <int K, bool NEG>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     const uint64_t *__restrict__ idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
     const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols, int32_t P,
-    int64_t n_entries, uint64_t *__restrict__ masks, int32_t *__restrict__ acc,
-    int32_t *__restrict__ flags) {
+    int64_t n_entries, int32_t sigma, const double *__restrict__ logt,
+    uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
+    int32_t *__restrict__ counts, double *__restrict__ fitness) {
     const int lane = threadIdx.x & 63;
     const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t total = (int64_t)P * W;
@@ -218,15 +271,16 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     const bool ok_range = start >= 0 && end <= n_entries && end > start;
     const int32_t L = ok_range ? (int32_t)(end - start) : 0;
 
-    // One lane per candidate validates every column and publishes the flag;
-    // other lanes only clamp column indices so that no read leaves the index.
+    // The lane of word 0 validates every column and reports the verdict with
+    // its part; other lanes only clamp column indices so that no read leaves
+    // the index.
+    bool bad = false;
     if (active && w == 0) {
-        int32_t bad = ok_range ? 0 : 1;
+        bad = !ok_range;
         for (int32_t t = 0; t < L; ++t) {
             const int32_t col = cols[start + t];
-            bad |= (col < 0 || col >= m) ? 1 : 0;
+            bad |= (col < 0 || col >= m);
         }
-        flags[c] = bad;
     }
 
     const uint64_t valid = (active && ok_range) ? tail_bits(n, w, W) : 0ull;
@@ -265,50 +319,23 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     }
 
     // Segmented sum over lanes of the same candidate (lanes hold consecutive
-    // items, so each candidate is one contiguous run of lanes), then one
-    // atomic per run.
-    int32_t cnt = __popcll(pos | neg);
+    // items, so each candidate is one contiguous run of lanes): the run's
+    // head gets the run's row count (low 16 bits, <= 64*64) and its number
+    // of words (high bits), then reports them once.
+    int32_t packed = active ? (__popcll(pos | neg) | (1 << 16)) : 0;
     const int32_t cc = (int32_t)c;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const int32_t v = __shfl_down(cnt, off);
+        const int32_t v = __shfl_down(packed, off);
         const int32_t oc = __shfl_down(cc, off);
-        if (lane + off < kWave && oc == cc) cnt += v;
+        if (lane + off < kWave && oc == cc) packed += v;
     }
     const int32_t prev_c = __shfl_up(cc, 1);
     const bool head = lane == 0 || prev_c != cc;
-    if (active && head && cnt) atomicAdd(acc + c, cnt);
-}
-
-// --------------------------------------------------------------- finalize --
-//
-// counts and Eq. (1).  ln(count-1) comes from a table built on the host with
-// the C library's log; L * ln is one rounded FP64 product and 2^e is an exact
-// scaling, so the result equals the host formula bit for bit.
-__global__ __launch_bounds__(kBlock) void finalize_kernel(int32_t P, int32_t sigma,
-                                                          const int32_t *__restrict__ offsets,
-                                                          const double *__restrict__ logt,
-                                                          int32_t *__restrict__ acc,
-                                                          const int32_t *__restrict__ flags,
-                                                          int32_t *__restrict__ counts,
-                                                          double *__restrict__ fitness) {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= P) return;
-    const int32_t cnt = acc[c];
-    acc[c] = 0;
-    if (flags[c]) {
-        counts[c] = -1;
-        fitness[c] = __builtin_nan("");
-        return;
-    }
-    const int32_t L = offsets[c + 1] - offsets[c];
-    counts[c] = cnt;
-    double f = 0.0;
-    if (cnt > 1) {
-        const int32_t e = cnt - sigma < 0 ? cnt - sigma : 0;
-        f = ldexp((double)L * logt[cnt - 1], e);
-    }
-    fitness[c] = f;
+    // word 0 is always the first lane of its run, hence a head itself.
+    if (active && head)
+        finish_part(c, (uint32_t)(packed & 0xFFFF), bad, packed >> 16, W, L, sigma, logt, acc,
+                    counts, fitness);
 }
 
 }  // namespace
@@ -346,10 +373,12 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
     const dim3 grid((unsigned)((int64_t)e.P * S));
     if (e.negative)
         hipLaunchKernelGGL(eval_direct_kernel<true>, grid, dim3(kBlock), 0, stream, a, n, npad, m,
-                           W, S, e.offsets, e.cols, e.n_entries, e.k, e.masks, e.acc, e.flags);
+                           W, S, e.offsets, e.cols, e.n_entries, e.k, e.sigma, e.logt, e.masks,
+                           e.acc, e.counts, e.fitness);
     else
         hipLaunchKernelGGL(eval_direct_kernel<false>, grid, dim3(kBlock), 0, stream, a, n, npad,
-                           m, W, S, e.offsets, e.cols, e.n_entries, e.k, e.masks, e.acc, e.flags);
+                           m, W, S, e.offsets, e.cols, e.n_entries, e.k, e.sigma, e.logt, e.masks,
+                           e.acc, e.counts, e.fitness);
     return hipGetLastError();
 }
 
@@ -360,11 +389,12 @@ static void launch_index_k(const uint64_t *idx, int64_t n, int32_t m, int64_t W,
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
     if (e.negative)
         hipLaunchKernelGGL((eval_index_kernel<K, true>), grid, dim3(kBlock), 0, stream, idx, n, m,
-                           W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.masks, e.acc, e.flags);
+                           W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt, e.masks,
+                           e.acc, e.counts, e.fitness);
     else
         hipLaunchKernelGGL((eval_index_kernel<K, false>), grid, dim3(kBlock), 0, stream, idx, n,
-                           m, W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.masks, e.acc,
-                           e.flags);
+                           m, W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
+                           e.masks, e.acc, e.counts, e.fitness);
 }
 
 hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
@@ -376,13 +406,6 @@ hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t 
     case 3: launch_index_k<3>(idx, n, m, W, wpad, e, stream); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize(const double *logt, const EvalArgs &e, hipStream_t stream) {
-    const dim3 grid((unsigned)((e.P + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(finalize_kernel, grid, dim3(kBlock), 0, stream, e.P, e.sigma, e.offsets,
-                       logt, e.acc, e.flags, e.counts, e.fitness);
     return hipGetLastError();
 }
 

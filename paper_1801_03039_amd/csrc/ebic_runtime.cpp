@@ -71,13 +71,7 @@ ebic_status grow(ebic_ctx *ctx, T *&ptr, int64_t &cap, int64_t need, bool zero) 
 }
 
 ebic_status ensure_scratch(ebic_ctx *ctx, int64_t P) {
-    int64_t cap_acc = ctx->cap_P, cap_flags = ctx->cap_P;
-    ebic_status st = grow(ctx, ctx->d_acc, cap_acc, P, true);
-    if (st != EBIC_OK) return st;
-    st = grow(ctx, ctx->d_flags, cap_flags, P, false);
-    if (st != EBIC_OK) return st;
-    ctx->cap_P = std::min(cap_acc, cap_flags);
-    return EBIC_OK;
+    return grow(ctx, ctx->d_acc, ctx->cap_P, P, true);
 }
 
 int64_t index_bytes_for(int32_t m, int64_t wpad) {
@@ -149,7 +143,6 @@ ebic_status launch_all(ebic_ctx *ctx, const EvalArgs &e, bool use_index, hipStre
         HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->n, ctx->m, ctx->W, ctx->wpad, e, s));
     else
         HIP_TRY(ctx, launch_eval_direct(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, e, s));
-    HIP_TRY(ctx, launch_finalize(ctx->d_log, e, s));
     return EBIC_OK;
 }
 
@@ -261,6 +254,10 @@ bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
 
 }  // namespace
 
+namespace ebic {
+void set_thread_error(const char *msg) { g_tls_error = msg; }
+}  // namespace ebic
+
 extern "C" {
 
 int64_t ebic_mask_words(int64_t n_rows) { return n_rows <= 0 ? 0 : words_of(n_rows); }
@@ -279,7 +276,7 @@ ebic_status ebic_destroy(ebic_ctx *ctx) {
     if (!ctx) return EBIC_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_acc, ctx->d_flags, ctx->d_off,
+    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_acc, ctx->d_off,
                     ctx->d_cols, ctx->d_counts, ctx->d_fit, ctx->d_masks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -338,10 +335,10 @@ ebic_status ebic_evaluate_device(ebic_ctx *ctx, const int32_t *d_offsets, const 
     bool use_index = false;
     st = choose_path(ctx, params, &use_index);
     if (st != EBIC_OK) return st;
-    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
     EvalArgs e{d_offsets, d_cols, P, n_entries, params->sigma, params->max_violations,
                params->negative_trends ? 1 : 0, params->want_masks ? d_masks : nullptr,
-               d_counts, d_fitness, ctx->d_acc, ctx->d_flags};
+               d_counts, d_fitness, ctx->d_log, ctx->d_acc};
     return launch_all(ctx, e, use_index, s);
 }
 
@@ -380,7 +377,7 @@ ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *
                                 hipMemcpyHostToDevice, s));
     EvalArgs e{ctx->d_off, ctx->d_cols, P, n_entries, params->sigma, params->max_violations,
                params->negative_trends ? 1 : 0, mask_words ? ctx->d_masks : nullptr,
-               ctx->d_counts, ctx->d_fit, ctx->d_acc, ctx->d_flags};
+               ctx->d_counts, ctx->d_fit, ctx->d_log, ctx->d_acc};
     if ((st = launch_all(ctx, e, use_index, s)) != EBIC_OK) return st;
     HIP_TRY(ctx, hipMemcpyAsync(counts, ctx->d_counts, sizeof(int32_t) * (size_t)P,
                                 hipMemcpyDeviceToHost, s));

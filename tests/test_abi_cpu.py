@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "ebic.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"\b(ebic_[a-z_]+)\s*\(", src))
+    names = set(re.findall(r"\b(ebic_[a-z_]+)\s*\((?!\s*\*)", src))
     # typedef'd callback types are not functions
     names -= set(re.findall(r"\(\s*\*\s*(ebic_[a-z_]+)\s*\)", src))
     return sorted(names)
@@ -58,3 +58,18 @@ def test_create_argument_errors_before_device_work():
                               None) == b.EBIC_E_ARG
     assert b._destroy(None) == b.EBIC_OK
     assert b._set_path(None, 0) == b.EBIC_E_ARG
+
+
+def test_one_hip_runtime_per_process():
+    # The package must bind libebic to the HIP runtime torch already loaded
+    # (same SONAME), never bring in a second one.
+    import subprocess
+    import sys
+    code = ("import paper_1801_03039_amd, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+            "print(len(libs), libs)\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("1 "), out.stdout

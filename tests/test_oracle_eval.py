@@ -313,7 +313,8 @@ def test_values_read_by_brute_force():
         for neg in (False, True):
             off, cols = synth.pack_cbf(pop)
             res = oracle.evaluate(a, off, cols, sigma=0, max_violations=k,
-                                  negative_trends=neg, want_reads=True)
+                                  negative_trends=neg, want_reads=True, want_depth=True)
+            assert np.array_equal(res["depth"].sum(axis=1), res["reads"])
             for i, s in enumerate(pop):
                 total = 0
                 for r in range(a.shape[0]):
@@ -325,6 +326,7 @@ def test_values_read_by_brute_force():
                         if (not up_ok) and (not neg or not dn_ok):
                             d = t + 1
                             break
+                    assert res["depth"][i, r] == d
                     total += d
                 assert res["reads"][i] == total
 
