@@ -152,57 +152,115 @@ struct Evaluator {
     }
 };
 
-// Overlap of two column sets, |x & e| / min(|x|, |e|); `mark` holds a
-// stamp for every column of x.
-double overlap(const std::vector<uint32_t> &mark, uint32_t stamp, int32_t lx, const int32_t *e,
-               int32_t le) {
-    int32_t inter = 0;
-    for (int32_t i = 0; i < le; ++i) inter += mark[(size_t)e[i]] == stamp;
-    return (double)inter / (double)std::min(lx, le);
-}
-
 // Step 5: the top-rank list update.
-void update_top(std::vector<TopEntry> &top, const Pop &pop, double theta, int32_t K,
-                std::vector<uint32_t> &mark, uint32_t &stamp) {
-    const int32_t P = pop.size();
-    std::vector<int32_t> order((size_t)P);
-    for (int32_t i = 0; i < P; ++i) order[(size_t)i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return pop.fit[(size_t)a] > pop.fit[(size_t)b]; });
-    for (int32_t i : order) {
-        const double fx = pop.fit[(size_t)i];
-        if (!(fx > 0.0)) continue;
-        const int32_t *x = pop.series(i);
-        const int32_t lx = pop.len(i);
-        bool listed = false;
-        for (const TopEntry &e : top)
-            if ((int32_t)e.s.size() == lx && std::equal(e.s.begin(), e.s.end(), x)) {
-                listed = true;
-                break;
+//
+// Members are visited by decreasing fitness (stable).  A member is skipped
+// when its fitness is not positive or its series is already listed; it is
+// rejected when a listed entry of at least its fitness overlaps it by more
+// than theta (|x & e| / min(|x|, |e|) on column sets); otherwise it evicts
+// the weaker entries it overlaps by more than theta and joins the list.  The
+// list is then sorted by fitness (stable) and cut to K.
+//
+// Only entries sharing a column with x can overlap it (or equal it), so the
+// intersections are accumulated through a column -> entries index instead of
+// comparing x with every entry; the decisions are the same.
+//
+// The pass also stops as soon as its outcome is fixed.  An entry can only be
+// evicted by a strictly fitter member, and members come by decreasing
+// fitness; so when x is reached, every live entry with fitness >= f(x) stays
+// live to the end and precedes x (and everything after x) in the final
+// stable order.  Once there are K of them, no later member can enter the
+// final K or remove one of them, and whatever it evicts has fitness < f(x)
+// and falls beyond the cut anyway.
+class TopRank {
+  public:
+    explicit TopRank(int32_t n_cols) : by_col_((size_t)n_cols) {}
+
+    const std::vector<TopEntry> &entries() const { return top_; }
+
+    void update(const Pop &pop, double theta, int32_t K) {
+        const int32_t P = pop.size();
+        order_.resize((size_t)P);
+        for (int32_t i = 0; i < P; ++i) order_[(size_t)i] = i;
+        std::stable_sort(order_.begin(), order_.end(), [&](int32_t a, int32_t b) {
+            return pop.fit[(size_t)a] > pop.fit[(size_t)b];
+        });
+        // working list: top_ in insertion order, plus liveness and the index
+        alive_.assign(top_.size(), 1);
+        for (auto &v : by_col_) v.clear();
+        for (size_t e = 0; e < top_.size(); ++e)
+            for (int32_t c : top_[e].s) by_col_[(size_t)c].push_back((int32_t)e);
+
+        const size_t n_old = top_.size();  // sorted by decreasing fitness
+        size_t old_ptr = 0;
+        int32_t settled = 0;                // live entries with fitness >= f(x)
+        for (int32_t i : order_) {
+            const double fx = pop.fit[(size_t)i];
+            if (!(fx > 0.0)) break;         // the rest are not positive either
+            for (; old_ptr < n_old && top_[old_ptr].fit >= fx; ++old_ptr)
+                settled += alive_[old_ptr];
+            if (settled >= K) break;
+            const int32_t *x = pop.series(i);
+            const int32_t lx = pop.len(i);
+            // intersections with every entry sharing a column with x
+            touched_.clear();
+            if (inter_.size() < top_.size()) inter_.resize(top_.size(), 0);
+            for (int32_t t = 0; t < lx; ++t)
+                for (int32_t e : by_col_[(size_t)x[t]]) {
+                    if (!alive_[(size_t)e]) continue;
+                    if (inter_[(size_t)e]++ == 0) touched_.push_back(e);
+                }
+            bool listed = false, blocked = false;
+            for (int32_t e : touched_) {
+                const TopEntry &te = top_[(size_t)e];
+                const int32_t le = (int32_t)te.s.size();
+                if (inter_[(size_t)e] == lx && le == lx && std::equal(te.s.begin(), te.s.end(), x))
+                    listed = true;
             }
-        if (listed) continue;
-        ++stamp;
-        for (int32_t t = 0; t < lx; ++t) mark[(size_t)x[t]] = stamp;
-        bool blocked = false;
-        for (const TopEntry &e : top)
-            if (e.fit >= fx && overlap(mark, stamp, lx, e.s.data(), (int32_t)e.s.size()) > theta) {
-                blocked = true;
-                break;
+            if (!listed)
+                for (int32_t e : touched_) {
+                    const TopEntry &te = top_[(size_t)e];
+                    const double ov = (double)inter_[(size_t)e] /
+                                      (double)std::min(lx, (int32_t)te.s.size());
+                    if (te.fit >= fx && ov > theta) {
+                        blocked = true;
+                        break;
+                    }
+                }
+            if (!listed && !blocked) {
+                for (int32_t e : touched_) {
+                    const TopEntry &te = top_[(size_t)e];
+                    const double ov = (double)inter_[(size_t)e] /
+                                      (double)std::min(lx, (int32_t)te.s.size());
+                    if (te.fit < fx && ov > theta) alive_[(size_t)e] = 0;
+                }
+                const int32_t id = (int32_t)top_.size();
+                top_.push_back(TopEntry{std::vector<int32_t>(x, x + lx), pop.counts[(size_t)i], fx});
+                alive_.push_back(1);
+                ++settled;                  // f(x) >= the fitness of every later member
+                for (int32_t t = 0; t < lx; ++t) by_col_[(size_t)x[t]].push_back(id);
             }
-        if (blocked) continue;
-        top.erase(std::remove_if(top.begin(), top.end(),
-                                 [&](const TopEntry &e) {
-                                     return e.fit < fx &&
-                                            overlap(mark, stamp, lx, e.s.data(),
-                                                    (int32_t)e.s.size()) > theta;
-                                 }),
-                  top.end());
-        top.push_back(TopEntry{std::vector<int32_t>(x, x + lx), pop.counts[(size_t)i], fx});
+            for (int32_t e : touched_) inter_[(size_t)e] = 0;
+        }
+        // compact (insertion order kept), stable sort by fitness, cut to K
+        size_t k = 0;
+        for (size_t e = 0; e < top_.size(); ++e)
+            if (alive_[e]) {
+                if (k != e) top_[k] = std::move(top_[e]);
+                ++k;
+            }
+        top_.resize(k);
+        std::stable_sort(top_.begin(), top_.end(),
+                         [](const TopEntry &a, const TopEntry &b) { return a.fit > b.fit; });
+        if ((int32_t)top_.size() > K) top_.resize((size_t)K);
     }
-    std::stable_sort(top.begin(), top.end(),
-                     [](const TopEntry &a, const TopEntry &b) { return a.fit > b.fit; });
-    if ((int32_t)top.size() > K) top.resize((size_t)K);
-}
+
+  private:
+    std::vector<TopEntry> top_;
+    std::vector<std::vector<int32_t>> by_col_;
+    std::vector<uint8_t> alive_;
+    std::vector<int32_t> inter_, touched_, order_;
+};
 
 bool contains(const std::vector<int32_t> &s, int32_t c) {
     return std::find(s.begin(), s.end(), c) != s.end();
@@ -334,8 +392,7 @@ ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t
     const int64_t W = (n_rows + 63) / 64;
     SplitMix64 rng(seed);
     Tabu tabu;
-    std::vector<uint32_t> mark((size_t)M, 0);
-    uint32_t stamp = 0;
+    TopRank toprank(M);
     ebic_params evalp = p.eval;
     evalp.want_masks = 0;
 
@@ -363,8 +420,8 @@ ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t
     ebic_status st = ev(prev, 0, &evalp, nullptr, prev.counts.data(), prev.fit.data());
     if (st != EBIC_OK) return st;
     emit(0, prev);
-    std::vector<TopEntry> top;
-    update_top(top, prev, p.overlap, p.toplist_size, mark, stamp);
+    toprank.update(prev, p.overlap, p.toplist_size);
+    const std::vector<TopEntry> &top = toprank.entries();
 
     int64_t wsum = 0;
     for (int i = 0; i < 5; ++i) wsum += p.op_weight[i];
@@ -444,7 +501,7 @@ ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t
         emit(g, cur);
         gens_run = g;
         // Step 5: top-rank list.
-        update_top(top, cur, p.overlap, p.toplist_size, mark, stamp);
+        toprank.update(cur, p.overlap, p.toplist_size);
         std::swap(prev, cur);
     }
 

@@ -247,12 +247,34 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 
 // -------------------------------------------------------- index evaluator --
 //
-// Thread = (candidate c, 64-row word w), flattened c-major over the grid.
-// Per consecutive pair (p, q) it reads lt(p,q) -- and lt(q,p) for the
-// falling direction -- from the pairwise order index and folds the violation
-// words (complements) into K+1 saturating bit-sliced counters per direction:
-// cnt[i] has bit b set when row b has more than i violations.  A lane stops
-// once every row of its word is rejected in every enabled direction.
+// Thread = (candidate c, 64-row word w), flattened c-major over the grid, so
+// every lane has work whatever W is.  The workgroup first stages the CBF
+// columns of the candidates it covers in LDS.  Per consecutive pair (p, q) a
+// lane reads lt(p,q) -- and lt(q,p) for the falling direction -- from the
+// pairwise order index and folds the violation words (complements) into K+1
+// saturating bit-sliced counters per direction: c[i] has bit b set when row
+// b has more than i violations.  Loads for kUnroll pairs are issued before
+// any is consumed (the lane's latency chain is one order-word round trip per
+// kUnroll pairs), and a lane stops once every row of its word is rejected in
+// every enabled direction.
+constexpr int kIdxLds = 4096;   // staged column entries per workgroup
+constexpr int kUnroll = 4;
+
+template <int K, bool NEG>
+__device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1], uint64_t lt_pq,
+                                     uint64_t lt_qp) {
+    const uint64_t vu = ~lt_pq;
+#pragma unroll
+    for (int i = K; i > 0; --i) cu[i] |= cu[i - 1] & vu;
+    cu[0] |= vu;
+    if (NEG) {
+        const uint64_t vd = ~lt_qp;
+#pragma unroll
+        for (int i = K; i > 0; --i) cd[i] |= cd[i - 1] & vd;
+        cd[0] |= vd;
+    }
+}
+
 template <int K, bool NEG>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     const uint64_t *__restrict__ idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
@@ -260,16 +282,35 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     int64_t n_entries, int32_t sigma, const double *__restrict__ logt,
     uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
     int32_t *__restrict__ counts, double *__restrict__ fitness) {
-    const int lane = threadIdx.x & 63;
-    const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t total = (int64_t)P * W;
+    __shared__ int32_t s_cols[kIdxLds];
+    const int tid = threadIdx.x, lane = tid & 63;
+    // The launcher guarantees P * W < 2^32.
+    const uint32_t Wu = (uint32_t)W;
+    const uint32_t item = blockIdx.x * (uint32_t)kBlock + (uint32_t)tid;
+    const uint32_t total = (uint32_t)P * Wu;
     const bool active = item < total;
-    const int64_t c = active ? item / W : (int64_t)P - 1;
-    const int64_t w = active ? item - c * W : 0;
+    const uint32_t c = active ? item / Wu : (uint32_t)P - 1;
+    const uint32_t w = active ? item - c * Wu : 0;
+
+    // Stage the columns of candidates [c_lo, c_hi] (uniform decision).
+    const uint32_t i0 = blockIdx.x * (uint32_t)kBlock;
+    const uint32_t c_lo = i0 / Wu;
+    const uint32_t c_hi = min((i0 + kBlock - 1) / Wu, (uint32_t)P - 1);
+    const int64_t b0 = offsets[c_lo], b1 = offsets[c_hi + 1];
+    const bool staged = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
+    if (staged) {
+        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += kBlock) s_cols[e] = cols[b0 + e];
+        __syncthreads();
+    }
 
     const int64_t start = offsets[c], end = offsets[c + 1];
     const bool ok_range = start >= 0 && end <= n_entries && end > start;
     const int32_t L = ok_range ? (int32_t)(end - start) : 0;
+    const bool in_lds = staged && start >= b0 && end <= b1;
+    const int32_t lds0 = (int32_t)(start - b0);
+    auto col_at = [&](int32_t t) -> int32_t {
+        return in_lds ? s_cols[lds0 + t] : cols[start + t];
+    };
 
     // The lane of word 0 validates every column and reports the verdict with
     // its part; other lanes only clamp column indices so that no read leaves
@@ -278,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     if (active && w == 0) {
         bad = !ok_range;
         for (int32_t t = 0; t < L; ++t) {
-            const int32_t col = cols[start + t];
+            const int32_t col = col_at(t);
             bad |= (col < 0 || col >= m);
         }
     }
@@ -289,33 +330,43 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     for (int i = 0; i <= K; ++i) cu[i] = cd[i] = 0ull;
 
     if (valid) {
-        const int32_t *sc = cols + start;
-        int32_t p = sc[0];
+        const uint64_t *base = idx + w;
+        int32_t p = col_at(0);
         p = (p < 0 || p >= m) ? 0 : p;
-        for (int32_t t = 1; t < L; ++t) {
-            int32_t q = sc[t];
-            q = (q < 0 || q >= m) ? 0 : q;
-            const uint64_t vu = ~idx[((int64_t)p * m + q) * wpad + w];
+        for (int32_t t = 1; t < L; t += kUnroll) {
+            int32_t q[kUnroll];
+            uint64_t lu[kUnroll], ld[kUnroll];
 #pragma unroll
-            for (int i = K; i > 0; --i) cu[i] |= cu[i - 1] & vu;
-            cu[0] |= vu;
-            uint64_t dead = cu[K];
-            if (NEG) {
-                const uint64_t vd = ~idx[((int64_t)q * m + p) * wpad + w];
-#pragma unroll
-                for (int i = K; i > 0; --i) cd[i] |= cd[i - 1] & vd;
-                cd[0] |= vd;
-                dead &= cd[K];
+            for (int u = 0; u < kUnroll; ++u) {
+                q[u] = 0;
+                if (t + u < L) {
+                    const int32_t v = col_at(t + u);
+                    q[u] = (v < 0 || v >= m) ? 0 : v;
+                }
             }
-            p = q;
+            int32_t pp = p;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                lu[u] = ~0ull;
+                ld[u] = ~0ull;
+                if (t + u < L) {
+                    lu[u] = base[((int64_t)pp * m + q[u]) * wpad];
+                    if (NEG) ld[u] = base[((int64_t)q[u] * m + pp) * wpad];
+                    pp = q[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) fold<K, NEG>(cu, cd, lu[u], ld[u]);
+            p = pp;
+            const uint64_t dead = NEG ? (cu[K] & cd[K]) : cu[K];
             if ((valid & ~dead) == 0ull) break;
         }
     }
     const uint64_t pos = valid & ~cu[K];
     const uint64_t neg = NEG ? (valid & ~cd[K]) : 0ull;
     if (masks && active) {
-        masks[(c * 2 + 0) * W + w] = pos;
-        masks[(c * 2 + 1) * W + w] = neg;
+        masks[((int64_t)c * 2 + 0) * W + w] = pos;
+        masks[((int64_t)c * 2 + 1) * W + w] = neg;
     }
 
     // Segmented sum over lanes of the same candidate (lanes hold consecutive

@@ -117,3 +117,13 @@ def test_argument_errors():
     with pytest.raises(E.EbicError) as ex:
         E.evolve_with(ev, 10, 4, 0, 1, cfg)
     assert ex.value.status == 2
+
+
+@pytest.mark.parametrize("theta,K", [(0.0, 5), (0.3, 3), (0.5, 1), (1.0, 4)])
+def test_top_rank_ties_and_small_lists(theta, K):
+    # Tie-heavy integer data: many members share counts and fitness, so the
+    # stable tie rules and the list cut are exercised every generation.
+    rng = np.random.default_rng(int(theta * 10) + K)
+    a = rng.integers(0, 3, size=(150, 12)).astype(np.float32)
+    cfg, op = _configs(60, 2, 5, (4, 0, True), (4, 1, True), overlap=theta, toplist_size=K)
+    _compare(a, 3, 12, cfg, op)
