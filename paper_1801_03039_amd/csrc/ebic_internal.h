@@ -29,8 +29,9 @@ struct DeviceBuf {
 hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int32_t layout,
                          int64_t npad, float *dst, hipStream_t stream);
 
+// Builds the pairwise order index and its per-pair tie flags (m*m bytes).
 hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
-                              int64_t wpad, uint64_t *idx, hipStream_t stream);
+                              int64_t wpad, uint64_t *idx, uint8_t *tie, hipStream_t stream);
 
 struct EvalArgs {
     const int32_t *offsets;
@@ -50,8 +51,8 @@ struct EvalArgs {
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               const EvalArgs &e, hipStream_t stream);
 
-hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
-                             const EvalArgs &e, hipStream_t stream);
+hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
+                             int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream);
 
 }  // namespace ebic
 
@@ -64,6 +65,7 @@ struct ebic_ctx {
     double *d_log = nullptr;     // ln(i), i = 0..n
     // pairwise order index
     uint64_t *d_idx = nullptr;
+    uint8_t *d_tie = nullptr;    // m*m tie flags of the index
     int64_t idx_bytes = 0;
     int64_t idx_budget = 0;
     bool idx_built = false;

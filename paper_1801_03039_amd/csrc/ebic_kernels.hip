@@ -111,6 +111,30 @@ __global__ __launch_bounds__(kBlock) void index_build_kernel(const float *__rest
     }
 }
 
+// Tie flags: tie[p*m + q] = 1 when some row r < n has a[r,p] and a[r,q]
+// equal or unordered (NaN), i.e. when neither lt(p,q) nor lt(q,p) holds.
+// For a pair without such a row the falling test needs no second order
+// word: lt(q,p) = ~lt(p,q) on every row.  One wave per ordered pair, lanes
+// over words.
+__global__ __launch_bounds__(kBlock) void tie_flags_kernel(const uint64_t *__restrict__ idx,
+                                                           int64_t n, int32_t m, int64_t W,
+                                                           int64_t wpad,
+                                                           uint8_t *__restrict__ tie) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t pair = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+         pair < (int64_t)m * m; pair += waves) {  // uniform per wave
+        const int64_t p = pair / m, q = pair - p * m;
+        const uint64_t *pq = idx + pair * wpad;
+        const uint64_t *qp = idx + (q * m + p) * wpad;
+        bool any = false;
+        for (int64_t w = lane; w < W; w += kWave)
+            any |= (~(pq[w] | qp[w]) & tail_bits(n, w, W)) != 0ull;
+        const uint64_t hit = ballot(any);
+        if (lane == 0) tie[pair] = hit ? 1 : 0;
+    }
+}
+
 // --------------------------------------------------------- fitness (Eq. 1) --
 //
 // Each part of a candidate (a workgroup's row slice, or a run of 64-row
@@ -253,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 // lane reads lt(p,q) -- and lt(q,p) for the falling direction -- from the
 // pairwise order index and folds the violation words (complements) into K+1
 // saturating bit-sliced counters per direction: c[i] has bit b set when row
-// b has more than i violations.  Loads for kUnroll pairs are issued before
+// b has more than i violations.  lt(q,p) is read only for pairs whose tie
+// flag is set; otherwise it is ~lt(p,q).  Loads for kUnroll pairs are issued before
 // any is consumed (the lane's latency chain is one order-word round trip per
 // kUnroll pairs), and a lane stops once every row of its word is rejected in
 // every enabled direction.
@@ -278,10 +303,11 @@ __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1
 template <int K, bool NEG>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     const uint64_t *__restrict__ idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
-    const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols, int32_t P,
-    int64_t n_entries, int32_t sigma, const double *__restrict__ logt,
-    uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
-    int32_t *__restrict__ counts, double *__restrict__ fitness) {
+    const uint8_t *__restrict__ tie, const int32_t *__restrict__ offsets,
+    const int32_t *__restrict__ cols, int32_t P, int64_t n_entries, int32_t sigma,
+    const double *__restrict__ logt, uint64_t *__restrict__ masks,
+    unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
+    double *__restrict__ fitness) {
     __shared__ int32_t s_cols[kIdxLds];
     const int tid = threadIdx.x, lane = tid & 63;
     // The launcher guarantees P * W < 2^32.
@@ -345,14 +371,28 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
                 }
             }
             int32_t pp = p;
+            uint8_t tf[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 lu[u] = ~0ull;
                 ld[u] = ~0ull;
+                tf[u] = 0;
                 if (t + u < L) {
-                    lu[u] = base[((int64_t)pp * m + q[u]) * wpad];
-                    if (NEG) ld[u] = base[((int64_t)q[u] * m + pp) * wpad];
+                    const int64_t pq = (int64_t)pp * m + q[u];
+                    lu[u] = base[pq * wpad];
+                    if (NEG) tf[u] = tie[pq];
                     pp = q[u];
+                }
+            }
+            if (NEG) {
+                // lt(q,p) is the complement of lt(p,q) unless the pair ties.
+                pp = p;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (t + u < L) {
+                        ld[u] = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
+                        pp = q[u];
+                    }
                 }
             }
 #pragma unroll
@@ -410,11 +450,19 @@ hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int
 }
 
 hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
-                              int64_t wpad, uint64_t *idx, hipStream_t stream) {
+                              int64_t wpad, uint64_t *idx, uint8_t *tie, hipStream_t stream) {
     const int64_t wblocks = (W + 3) / 4;
     const int64_t pblocks = (m + kPB - 1) / kPB;
     hipLaunchKernelGGL(index_build_kernel, dim3((unsigned)(wblocks * pblocks)), dim3(kBlock), 0,
                        stream, a, n, npad, m, W, wpad, wblocks, idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t pairs = (int64_t)m * m;
+    const int64_t waves_per_block = kBlock / kWave;
+    int64_t blocks = (pairs + waves_per_block - 1) / waves_per_block;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(tie_flags_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, idx, n, m,
+                       W, wpad, tie);
     return hipGetLastError();
 }
 
@@ -434,27 +482,27 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
 }
 
 template <int K>
-static void launch_index_k(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
-                           const EvalArgs &e, hipStream_t stream) {
+static void launch_index_k(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
+                           int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream) {
     const int64_t total = (int64_t)e.P * W;
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
     if (e.negative)
         hipLaunchKernelGGL((eval_index_kernel<K, true>), grid, dim3(kBlock), 0, stream, idx, n, m,
-                           W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt, e.masks,
-                           e.acc, e.counts, e.fitness);
+                           W, wpad, tie, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
+                           e.masks, e.acc, e.counts, e.fitness);
     else
         hipLaunchKernelGGL((eval_index_kernel<K, false>), grid, dim3(kBlock), 0, stream, idx, n,
-                           m, W, wpad, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
+                           m, W, wpad, tie, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
                            e.masks, e.acc, e.counts, e.fitness);
 }
 
-hipError_t launch_eval_index(const uint64_t *idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
-                             const EvalArgs &e, hipStream_t stream) {
+hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
+                             int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream) {
     switch (e.k) {
-    case 0: launch_index_k<0>(idx, n, m, W, wpad, e, stream); break;
-    case 1: launch_index_k<1>(idx, n, m, W, wpad, e, stream); break;
-    case 2: launch_index_k<2>(idx, n, m, W, wpad, e, stream); break;
-    case 3: launch_index_k<3>(idx, n, m, W, wpad, e, stream); break;
+    case 0: launch_index_k<0>(idx, tie, n, m, W, wpad, e, stream); break;
+    case 1: launch_index_k<1>(idx, tie, n, m, W, wpad, e, stream); break;
+    case 2: launch_index_k<2>(idx, tie, n, m, W, wpad, e, stream); break;
+    case 3: launch_index_k<3>(idx, tie, n, m, W, wpad, e, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

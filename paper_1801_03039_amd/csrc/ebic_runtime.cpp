@@ -75,7 +75,7 @@ ebic_status ensure_scratch(ebic_ctx *ctx, int64_t P) {
 }
 
 int64_t index_bytes_for(int32_t m, int64_t wpad) {
-    return (int64_t)m * (int64_t)m * wpad * 8;
+    return (int64_t)m * (int64_t)m * (wpad * 8 + 1);  // order words + tie flags
 }
 
 ebic_status build_index(ebic_ctx *ctx) {
@@ -83,20 +83,28 @@ ebic_status build_index(ebic_ctx *ctx) {
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (!ctx->d_idx) {
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, (size_t)ctx->idx_bytes);
+        hipError_t e = hipMalloc(&p, (size_t)ctx->m * (size_t)ctx->m * (size_t)ctx->wpad * 8);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(ctx, EBIC_E_NOMEM, "cannot allocate the pairwise order index (" +
                                                std::to_string(ctx->idx_bytes) + " bytes)");
         }
         ctx->d_idx = static_cast<uint64_t *>(p);
+        e = hipMalloc(&p, (size_t)ctx->m * (size_t)ctx->m);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(ctx->d_idx);
+            ctx->d_idx = nullptr;
+            return fail(ctx, EBIC_E_NOMEM, "cannot allocate the index tie flags");
+        }
+        ctx->d_tie = static_cast<uint8_t *>(p);
     }
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
     HIP_TRY(ctx, launch_index_build(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, ctx->wpad,
-                                    ctx->d_idx, ctx->stream));
+                                    ctx->d_idx, ctx->d_tie, ctx->stream));
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
@@ -140,7 +148,8 @@ ebic_status launch_all(ebic_ctx *ctx, const EvalArgs &e, bool use_index, hipStre
     if (items > kMaxLaunchThreads)
         return fail(ctx, EBIC_E_ARG, "population too large for one launch; split it");
     if (use_index)
-        HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->n, ctx->m, ctx->W, ctx->wpad, e, s));
+        HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->d_tie, ctx->n, ctx->m, ctx->W, ctx->wpad,
+                                       e, s));
     else
         HIP_TRY(ctx, launch_eval_direct(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, e, s));
     return EBIC_OK;
@@ -276,7 +285,7 @@ ebic_status ebic_destroy(ebic_ctx *ctx) {
     if (!ctx) return EBIC_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_acc, ctx->d_off,
+    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_tie, ctx->d_acc, ctx->d_off,
                     ctx->d_cols, ctx->d_counts, ctx->d_fit, ctx->d_masks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
