@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-direct", action="store_true", help="skip timing the direct path")
     ap.add_argument("--evolve-gens", type=int, default=-1, help="generations (-1: workload's)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed region, one device copy of this many MiB (a kernel of "
+                         "known traffic, to calibrate rocprof FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -93,24 +96,76 @@ def time_evaluations(ctx, dev, pops, w, steps, warmup, want_masks=False):
     return wall_ms, float(k_ms.mean()), per_pop
 
 
-def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks):
+def tie_pairs(a, series):
+    """For each candidate, a bool per consecutive pair: does some row hold
+    equal or unordered (NaN) values on the pair's two columns?  A property
+    of the input matrix; it decides whether the index path must read the
+    reverse order word for the falling direction."""
+    cache = {}
+    out = []
+    for s in series:
+        flags = []
+        for p, q in zip(s[:-1], s[1:]):
+            key = (int(p), int(q)) if p < q else (int(q), int(p))
+            if key not in cache:
+                x, y = a[:, key[0]], a[:, key[1]]
+                with np.errstate(invalid="ignore"):
+                    cache[key] = bool(np.any(~((x < y) | (x > y))))
+            flags.append(cache[key])
+        out.append(np.array(flags, dtype=bool))
+    return out
+
+
+def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks, ties=None):
     """Bytes each evaluator must move, from the oracle's exact per-row
     decision depths d(c, r) (values read before row r's decision is fixed).
 
     direct (row-level):  4 * sum d                 (FP32 values)
-    index (word-level):  8 * dirs * sum_{c,w} max_{r in w} (d - 1)
-                         (one 64-bit order word per pair, direction and
-                          64-row word, until every row of the word is decided)
+    index (word-level):  per (candidate, 64-row word), for each of the first
+                         k_w = max_{r in w} (d - 1) pairs (until every row of
+                         the word is decided): the 8-byte order word lt(p,q),
+                         plus, with falling trends on, the 8-byte word lt(q,p)
+                         when the pair has a tie and a 1-byte tie flag per
+                         (candidate, pair)
     both add the CBF (4 (P + 1 + sum L)) and outputs (4P + 8P, + 16 P W masks)."""
     W = (n + 63) // 64
     io = 4 * (P + 1 + sum_L) + 12 * P + (16 * P * W if want_masks else 0)
     b_seq = 4 * int(depth.sum(dtype=np.int64)) + io
     pad = np.zeros((P, W * 64), dtype=np.int32)
     pad[:, :n] = depth
-    pairs = np.clip(pad.reshape(P, W, 64).max(axis=2).astype(np.int64) - 1, 0, None)
-    dirs = 2 if negative else 1
-    b_idx = 8 * dirs * int(pairs.sum()) + io
+    pairs = np.clip(pad.reshape(P, W, 64).max(axis=2).astype(np.int64) - 1, 0, None)  # [P, W]
+    b_idx = 8 * int(pairs.sum()) + io
+    if negative:
+        for c in range(P):
+            t = ties[c]
+            if t.size and t.any():
+                cum = np.concatenate([[0], np.cumsum(t)])     # tie pairs among the first k
+                b_idx += 8 * int(cum[pairs[c]].sum())
+            b_idx += int(pairs[c].max(initial=0))              # tie flags
     return b_seq, b_idx
+
+
+def kernel_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1801_03039_amd", "csrc", "ebic_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprof counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    when it was not taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return int(kv["hbm_bytes_per_launch"])
 
 
 def main():
@@ -155,6 +210,12 @@ def main():
     log("timing evaluations")
     wall_ms, kern_ms, _ = time_evaluations(ctx, dev, pops, w, args.steps, args.warmup)
     value = P * N / (wall_ms * 1e-3) / 1e9
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        torch.cuda.synchronize(dev)
+        dst = src.clone()
+        torch.cuda.synchronize(dev)
+        del src, dst
 
     out = {
         "metric": "Gtrend-checks/s, candidates/s vs plain; surrogate speedup at equal fitness",
@@ -256,16 +317,22 @@ def main():
             "cpu": platform.processor() or platform.machine(),
         }
         out["vs_plain"] = round(value / out["cpu_baseline"]["value"], 1)
-        b_seq, b_idx = algorithmic_bytes(ref["depth"], N, P, sum_L, w.negative_trends, False)
+        ties = tie_pairs(a, pop) if (use_index and w.negative_trends) else None
+        b_seq, b_idx = algorithmic_bytes(ref["depth"], N, P, sum_L, w.negative_trends, False, ties)
         b_alg = b_idx if use_index else b_seq
         achieved = b_alg / (kern_ms * 1e-3) / 1e9
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("eval_index_kernel" if use_index else "eval_direct_kernel",
+                                        w.name),
             "kernel": "eval_index_kernel" if use_index else "eval_direct_kernel",
             "bytes_per_launch": b_alg,
-            "bytes_rule": ("8 B x dirs per (candidate, 64-row word, pair) until the word is decided"
-                           if use_index else "4 B per FP32 value a row must read until decided"),
+            "bytes_rule": ("8 B order word per (candidate, 64-row word, pair) until the word is "
+                           "decided, +8 B reverse word on tie pairs and a 1 B tie flag per "
+                           "(candidate, pair) when falling trends are on; plus CBF and outputs"
+                           if use_index else "4 B per FP32 value a row must read until decided; "
+                           "plus CBF and outputs"),
         }
         # The byte count of the paper-level definition (values read row by
         # row), whatever evaluator ran.

@@ -273,6 +273,66 @@ ebic_status ebic_result_get(const ebic_result *r, int32_t i, const int32_t **col
 ebic_status ebic_result_stats(const ebic_result *r, ebic_run_stats *stats);
 void ebic_result_free(ebic_result *r);
 
+/*
+ * Batched EBIC: many independent runs, each on its own matrix (any shapes),
+ * sharing one GPU launch per generation.  Each run behaves exactly as
+ * ebic_evolve on its own context with its own seed; the runs' populations
+ * are evaluated together by one persistent kernel that drains a queue of
+ * (run, candidate, 64-row word) tiles, launched through a captured HIP graph
+ * whose run table is refreshed in device memory each generation.  The host
+ * steps of the runs proceed on host threads.  Evaluation uses each run's
+ * pairwise order index (built at creation), so max_violations <= 3.
+ */
+typedef struct ebic_batch ebic_batch;
+
+/* matrices[r]: host row-major n_rows[r] x n_cols[r] FP32 (copied; the
+ * caller may free them on return).  Errors: E_ARG (n_runs < 1, null or bad
+ * sizes), E_NOMEM (a matrix or its order index does not fit), E_DEVICE. */
+ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, const int64_t *n_rows,
+                              const int32_t *n_cols, int32_t device, ebic_batch **out);
+ebic_status ebic_batch_destroy(ebic_batch *b);
+
+/* Launch shape of the persistent kernel: `workgroups` persistent
+ * workgroups (0: one per resident slot) and `unroll` pairs per batch of
+ * loads (2, 4 or 8). */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ebic_batch_tuning) */
+    int32_t workgroups;
+    int32_t unroll;
+    double best_ms;             /* time of the chosen shape in the last tuning (0: untuned) */
+} ebic_batch_tuning;
+ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t);
+ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t);
+
+/*
+ * One population per run, evaluated in one launch (host arrays, blocking).
+ * offsets[r]/cols[r] is run r's CBF with P[r] candidates (P[r] = 0 skips
+ * the run); counts[r], fitness[r] receive P[r] values; masks may be NULL,
+ * else masks[r] receives 2*P[r]*ebic_mask_words(n_rows[r]) words when
+ * params->want_masks.  Same semantics and validation as ebic_evaluate.
+ * With tune = 1 the launch shape is first chosen by timing a set of
+ * candidate shapes on exactly this input (the autotuner); the result is
+ * kept for later calls.
+ */
+ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
+                                const int32_t *const *cols, const int32_t *P,
+                                const ebic_params *params, uint64_t *const *masks,
+                                int32_t *const *counts, double *const *fitness, int32_t tune);
+
+/* Runs ebic_evolve's algorithm for every run r with seeds[r]; results[r]
+ * receives run r's result (free each with ebic_result_free).  params is
+ * shared by all runs (its on_generation is ignored; use on_generation
+ * here, called with the run index, one call at a time).  host_threads <= 0
+ * picks the hardware concurrency.  The launch shape is tuned on the first
+ * generation unless set before. */
+typedef void (*ebic_batch_generation_fn)(void *user, int32_t run, int32_t gen,
+                                         const int32_t *offsets, const int32_t *cols, int32_t P,
+                                         const int32_t *counts, const double *fitness);
+ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t generations,
+                              const ebic_evolve_params *params,
+                              ebic_batch_generation_fn on_generation, void *user,
+                              int32_t host_threads, ebic_result **results);
+
 /* Message of the last error on ctx.  With ctx == NULL: the calling thread's
  * last error from a call that had no context (ebic_create*, argument errors
  * of ebic_evolve*, ebic_result_*); an evaluation failure inside

@@ -7,6 +7,7 @@ The library must be built (``python -m paper_1801_03039_amd.build``); there is
 no CPU fallback.
 """
 from .binding import (  # noqa: F401
+    Batch,
     Context,
     EbicError,
     EBIC_PATH_AUTO,

@@ -438,3 +438,135 @@ def evolve_with(evaluate: Callable, n_rows: int, n_cols: int, seed: int, generat
         raise errors[0]
     _check(st)
     return _finish(res, n_rows)
+
+
+# -------------------------------------------------------------- batched runs --
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("workgroups", _i32), ("unroll", _i32),
+                ("best_ms", _dbl)]
+
+
+BATCH_GENERATION_FN = ctypes.CFUNCTYPE(None, _vp, _i32, _i32, ctypes.POINTER(_i32),
+                                       ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32),
+                                       ctypes.POINTER(_dbl))
+_batch_create = _sig("ebic_batch_create", _i32, [_i32, _vp, _vp, _vp, _i32, _P(_vp)])
+_batch_destroy = _sig("ebic_batch_destroy", _i32, [_vp])
+_batch_get_tuning = _sig("ebic_batch_get_tuning", _i32, [_vp, _P(BatchTuning)])
+_batch_set_tuning = _sig("ebic_batch_set_tuning", _i32, [_vp, _P(BatchTuning)])
+_batch_evaluate = _sig("ebic_batch_evaluate", _i32,
+                       [_vp, _vp, _vp, _vp, _P(Params), _vp, _vp, _vp, _i32])
+_batch_evolve = _sig("ebic_batch_evolve", _i32,
+                     [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _i32, _vp])
+EXPORTED += ["ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
+             "ebic_batch_set_tuning", "ebic_batch_evaluate", "ebic_batch_evolve"]
+
+
+def _ptr_array(arrs, ctype):
+    out = (ctypes.c_void_p * len(arrs))()
+    for i, a in enumerate(arrs):
+        out[i] = None if a is None else a.ctypes.data
+    return out
+
+
+class Batch:
+    """Many matrices on one GPU, evaluated or evolved together (``ebic_batch_*``)."""
+
+    def __init__(self, matrices, device: int = 0):
+        mats = [np.ascontiguousarray(m, dtype=np.float32) for m in matrices]
+        n = np.array([m.shape[0] for m in mats], dtype=np.int64)
+        mcols = np.array([m.shape[1] for m in mats], dtype=np.int32)
+        ptrs = _ptr_array(mats, ctypes.c_float)
+        h = _vp()
+        _check(_batch_create(len(mats), ptrs, n.ctypes.data, mcols.ctypes.data, int(device),
+                             ctypes.byref(h)))
+        self._h = h
+        self.n_rows = [int(x) for x in n]
+        self.n_cols = [int(x) for x in mcols]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def tuning(self) -> dict:
+        t = BatchTuning()
+        t.struct_size = ctypes.sizeof(BatchTuning)
+        _check(_batch_get_tuning(self._h, ctypes.byref(t)))
+        return {"workgroups": t.workgroups, "unroll": t.unroll, "best_ms": t.best_ms}
+
+    def set_tuning(self, workgroups: int = 0, unroll: int = 4):
+        t = BatchTuning(ctypes.sizeof(BatchTuning), int(workgroups), int(unroll), 0.0)
+        _check(_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def evaluate(self, pops, *, sigma: int, max_violations: int = 0,
+                 negative_trends: bool = False, want_masks: bool = False, tune: bool = False):
+        """``pops[r]`` is (offsets, cols) for run r, or None to skip it.
+        Returns one dict (counts, fitness[, masks]) per run (None if skipped)."""
+        R = len(self.n_rows)
+        assert len(pops) == R
+        offs, cls, Ps, cnts, fits, msks = [], [], [], [], [], []
+        for r in range(R):
+            if pops[r] is None or len(pops[r][0]) <= 1:
+                offs.append(None); cls.append(None); Ps.append(0)
+                cnts.append(None); fits.append(None); msks.append(None)
+                continue
+            o = np.ascontiguousarray(pops[r][0], dtype=np.int32)
+            c = np.ascontiguousarray(pops[r][1], dtype=np.int32)
+            P = len(o) - 1
+            offs.append(o); cls.append(c); Ps.append(P)
+            cnts.append(np.zeros(P, dtype=np.int32)); fits.append(np.zeros(P, dtype=np.float64))
+            msks.append(np.zeros((P, 2, mask_words(self.n_rows[r])), dtype=np.uint64)
+                        if want_masks else None)
+        P_arr = np.array(Ps, dtype=np.int32)
+        prm = make_params(sigma, max_violations, negative_trends, want_masks)
+        _check(_batch_evaluate(self._h, _ptr_array(offs, None), _ptr_array(cls, None),
+                               P_arr.ctypes.data, ctypes.byref(prm),
+                               _ptr_array(msks, None) if want_masks else None,
+                               _ptr_array(cnts, None), _ptr_array(fits, None), int(bool(tune))))
+        out = []
+        for r in range(R):
+            if Ps[r] == 0:
+                out.append(None)
+                continue
+            d = {"counts": cnts[r], "fitness": fits[r]}
+            if want_masks:
+                d["masks"] = msks[r]
+            out.append(d)
+        return out
+
+    def evolve(self, seeds, generations: int, cfg: EvolveConfig, on_generation=None,
+               host_threads: int = 0):
+        """EBIC runs, one per matrix, seeds[r] for run r; returns one
+        EvolveResult per run.  ``on_generation(run, Generation)``."""
+        R = len(self.n_rows)
+        sd = np.array([int(s) & ((1 << 64) - 1) for s in seeds], dtype=np.uint64)
+        assert len(sd) == R
+        if on_generation is None:
+            gcb = BATCH_GENERATION_FN()
+        else:
+            def cb(user, run, gen, off, cols, P, counts, fit):
+                o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
+                n = int(o[-1])
+                c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+                on_generation(int(run), Generation(int(gen), o, c,
+                                                   np.ctypeslib.as_array(counts, shape=(P,)).copy(),
+                                                   np.ctypeslib.as_array(fit, shape=(P,)).copy()))
+            gcb = BATCH_GENERATION_FN(cb)
+        p = _params_c(cfg, GENERATION_FN())
+        res = (ctypes.c_void_p * R)()
+        _check(_batch_evolve(self._h, sd.ctypes.data, int(generations), ctypes.byref(p), gcb, None,
+                             int(host_threads), res))
+        return [_finish(_vp(res[r]), self.n_rows[r]) for r in range(R)]

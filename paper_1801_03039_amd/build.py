@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libebic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["ebic_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp"]
+SOURCES = ["ebic_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
           "-I", INCLUDE, "-I", CSRC]

@@ -1,0 +1,625 @@
+// Batched EBIC: many independent runs, one GPU launch per generation.
+//
+// Each run owns a context (its matrix, pairwise order index and ln table).
+// Per generation every active run builds its population on a host thread
+// (Steps 1-3); the new members of all runs are packed into one CBF with
+// global offsets, a run table describes where each run's candidates,
+// matrix index and outputs are, and one persistent kernel drains the queue
+// of (run, 64-row word) tiles (Step 4).  The run-table copy and the kernel
+// are a captured HIP graph, replayed each generation; the CBF and results
+// move with plain stream-ordered copies around it.  Step 5 then runs per
+// run on host threads.  Every run is exactly ebic_evolve on its own
+// context: same seed, same draws, same scores.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "ebic_internal.h"
+#include "ebic_run.h"
+
+using namespace ebic;
+using namespace ebic::host;
+
+struct ebic_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<ebic_ctx *> ctx;
+    // device buffers
+    IndexRun *d_runs = nullptr;
+    uint32_t *d_tile_base = nullptr;
+    unsigned int *d_work = nullptr;
+    int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr;
+    double *d_fit = nullptr;
+    unsigned long long *d_acc = nullptr;
+    uint64_t *d_masks = nullptr;
+    int64_t cap_cand = 0, cap_cols = 0, cap_masks = 0;
+    // pinned host staging
+    IndexRun *h_runs = nullptr;
+    uint32_t *h_tile_base = nullptr;
+    int32_t *h_off = nullptr, *h_cols = nullptr, *h_counts = nullptr;
+    double *h_fit = nullptr;
+    int64_t hcap_cand = 0, hcap_cols = 0;
+    // launch shape and its graph
+    int32_t resident_wgs = 0;       // workgroups resident at once (occupancy x CUs)
+    int32_t workgroups = 0, unroll = 4;
+    double tuned_ms = 0.0;
+    bool tuned = false;
+    hipGraphExec_t exec = nullptr;
+    BatchLaunch graph_key{};
+};
+
+namespace {
+
+ebic_status bfail(ebic_status st, const std::string &msg) {
+    set_thread_error(msg.c_str());
+    return st;
+}
+
+ebic_status bhip(hipError_t e, const char *what) {
+    return bfail(e == hipErrorOutOfMemory ? EBIC_E_NOMEM : EBIC_E_DEVICE,
+                 std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BHIP(expr)                                     \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return bhip(_e, #expr);  \
+    } while (0)
+
+void drop_graph(ebic_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+}
+
+template <typename T>
+ebic_status dgrow(ebic_batch *b, T *&p, int64_t need, int64_t &cap, bool zero) {
+    if (need <= cap) return EBIC_OK;
+    const int64_t ncap = std::max<int64_t>(need, cap * 2);
+    BHIP(hipStreamSynchronize(b->stream));
+    drop_graph(b);  // the graph holds the old pointers
+    if (p) BHIP(hipFree(p));
+    p = nullptr;
+    cap = 0;
+    BHIP(hipMalloc((void **)&p, sizeof(T) * (size_t)ncap));
+    if (zero) BHIP(hipMemset(p, 0, sizeof(T) * (size_t)ncap));
+    cap = ncap;
+    return EBIC_OK;
+}
+
+template <typename T>
+ebic_status hgrow(ebic_batch *b, T *&p, int64_t need, int64_t &cap) {
+    if (need <= cap) return EBIC_OK;
+    const int64_t ncap = std::max<int64_t>(need, cap * 2);
+    BHIP(hipStreamSynchronize(b->stream));
+    if (p) BHIP(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+    BHIP(hipHostMalloc((void **)&p, sizeof(T) * (size_t)ncap, hipHostMallocDefault));
+    cap = ncap;
+    return EBIC_OK;
+}
+
+// One batched evaluation request: run r evaluates P[r] candidates whose CBF
+// is already packed (global offsets) in the pinned staging buffers.
+struct Request {
+    std::vector<int32_t> P;   // per run
+    int64_t n_cand = 0, n_cols = 0;
+    const ebic_params *params = nullptr;
+    bool masks = false;
+};
+
+// Capacity for n candidates / n column entries / mask words.
+ebic_status reserve(ebic_batch *b, int64_t n_cand, int64_t n_cols, int64_t n_mask_words) {
+    int64_t c1 = b->cap_cand, c2 = b->cap_cand, c3 = b->cap_cand, c4 = b->cap_cand;
+    ebic_status st;
+    if ((st = dgrow(b, b->d_off, n_cand + 1, c1, false)) != EBIC_OK) return st;
+    if ((st = dgrow(b, b->d_counts, n_cand, c2, false)) != EBIC_OK) return st;
+    if ((st = dgrow(b, b->d_fit, n_cand, c3, false)) != EBIC_OK) return st;
+    if ((st = dgrow(b, b->d_acc, n_cand, c4, true)) != EBIC_OK) return st;
+    b->cap_cand = std::min(std::min(c1, c2), std::min(c3, c4));
+    if ((st = dgrow(b, b->d_cols, std::max<int64_t>(n_cols, 1), b->cap_cols, false)) != EBIC_OK)
+        return st;
+    if (n_mask_words &&
+        (st = dgrow(b, b->d_masks, n_mask_words, b->cap_masks, false)) != EBIC_OK)
+        return st;
+    int64_t h1 = b->hcap_cand, h2 = b->hcap_cand, h3 = b->hcap_cand;
+    if ((st = hgrow(b, b->h_off, n_cand + 1, h1)) != EBIC_OK) return st;
+    if ((st = hgrow(b, b->h_counts, n_cand, h2)) != EBIC_OK) return st;
+    if ((st = hgrow(b, b->h_fit, n_cand, h3)) != EBIC_OK) return st;
+    b->hcap_cand = std::min(h1, std::min(h2, h3));
+    return hgrow(b, b->h_cols, std::max<int64_t>(n_cols, 1), b->hcap_cols);
+}
+
+// Fills the run table for a request; returns the total number of tiles.
+uint64_t fill_runs(ebic_batch *b, const Request &q) {
+    const int32_t R = (int32_t)b->ctx.size();
+    int64_t cand = 0, maskw = 0;
+    uint64_t tiles = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        ebic_ctx *c = b->ctx[(size_t)r];
+        const int32_t P = q.P[(size_t)r];
+        b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
+                                maskw};
+        b->h_tile_base[r] = (uint32_t)tiles;
+        tiles += ((uint64_t)P * (uint64_t)c->W + 255) / 256;
+        cand += P;
+        if (q.masks) maskw += (int64_t)P * 2 * c->W;
+    }
+    b->h_tile_base[R] = (uint32_t)tiles;
+    return tiles;
+}
+
+BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll) {
+    BatchLaunch L{};
+    L.runs = b->d_runs;
+    L.tile_base = b->d_tile_base;
+    L.n_runs = (int32_t)b->ctx.size();
+    L.work = b->d_work;
+    L.offsets = b->d_off;
+    L.cols = b->d_cols;
+    // Bound for offsets checks: the allocated column buffer (stable across
+    // generations, so the captured graph stays valid; the host validated
+    // every CBF).
+    L.n_entries = b->cap_cols;
+    L.sigma = q.params->sigma;
+    L.k = q.params->max_violations;
+    L.negative = q.params->negative_trends ? 1 : 0;
+    L.masks = q.masks ? b->d_masks : nullptr;
+    L.acc = b->d_acc;
+    L.counts = b->d_counts;
+    L.fitness = b->d_fit;
+    L.grid = (uint32_t)workgroups;
+    L.unroll = unroll;
+    return L;
+}
+
+bool same_graph(const BatchLaunch &a, const BatchLaunch &x) {
+    // n_entries is a kernel argument too: the graph is re-made when it changes.
+    return a.runs == x.runs && a.tile_base == x.tile_base && a.work == x.work &&
+           a.offsets == x.offsets && a.cols == x.cols && a.n_entries == x.n_entries &&
+           a.sigma == x.sigma && a.k == x.k && a.negative == x.negative && a.masks == x.masks &&
+           a.acc == x.acc && a.counts == x.counts && a.fitness == x.fitness && a.grid == x.grid &&
+           a.unroll == x.unroll;
+}
+
+// Graph = [copy of the run table and tile bases (fixed size), kernel].
+ebic_status launch_graph(ebic_batch *b, const BatchLaunch &L) {
+    const size_t R = b->ctx.size();
+    if (!b->exec || !same_graph(b->graph_key, L)) {
+        drop_graph(b);
+        hipGraph_t g = nullptr;
+        BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipMemcpyAsync(b->d_runs, b->h_runs, sizeof(IndexRun) * R,
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_tile_base, b->h_tile_base, sizeof(uint32_t) * (R + 1),
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = launch_eval_index_batch(L, b->stream);
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bhip(e != hipSuccess ? e : e2, "graph capture");
+        }
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return bhip(e, "hipGraphInstantiate");
+        }
+        b->graph_key = L;
+    }
+    BHIP(hipGraphLaunch(b->exec, b->stream));
+    return EBIC_OK;
+}
+
+// Runs one packed request (CBF already in h_off/h_cols, P per run set).
+// Results land in h_counts/h_fit (and d_masks when asked).
+ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
+                        bool copy_back = true) {
+    const uint64_t tiles = fill_runs(b, q);
+    if (tiles == 0) return EBIC_OK;
+    BHIP(hipMemcpyAsync(b->d_off, b->h_off, sizeof(int32_t) * (size_t)(q.n_cand + 1),
+                        hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),
+                        hipMemcpyHostToDevice, b->stream));
+    ebic_status st = launch_graph(b, make_launch(b, q, std::max(1, workgroups), unroll));
+    if (st != EBIC_OK) return st;
+    if (copy_back) {
+        BHIP(hipMemcpyAsync(b->h_counts, b->d_counts, sizeof(int32_t) * (size_t)q.n_cand,
+                            hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(b->h_fit, b->d_fit, sizeof(double) * (size_t)q.n_cand,
+                            hipMemcpyDeviceToHost, b->stream));
+    }
+    BHIP(hipStreamSynchronize(b->stream));
+    return EBIC_OK;
+}
+
+// Autotuner: times candidate launch shapes on this very request and keeps
+// the fastest (median of a few replays each).  Shapes differ only in speed:
+// every shape computes the same results.
+ebic_status tune(ebic_batch *b, const Request &q) {
+    const uint64_t tiles = fill_runs(b, q);
+    if (tiles == 0) return EBIC_OK;
+    const int32_t full = b->resident_wgs;
+    std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full,
+                                  (int32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1),
+                                                              (uint64_t)1 << 20)};
+    const int32_t unrolls[] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int32_t best_g = full, best_u = 4;
+    for (int32_t u : unrolls)
+        for (int32_t g : grids) {
+            std::vector<float> t;
+            for (int rep = 0; rep < 4; ++rep) {
+                BHIP(hipEventRecord(e0, b->stream));
+                ebic_status st = run_request(b, q, g, u, false);
+                if (st != EBIC_OK) return st;
+                BHIP(hipEventRecord(e1, b->stream));
+                BHIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BHIP(hipEventElapsedTime(&ms, e0, e1));
+                t.push_back(ms);
+            }
+            std::sort(t.begin(), t.end());
+            const double med = 0.5 * (t[1] + t[2]);
+            if (med < best) {
+                best = med;
+                best_g = g;
+                best_u = u;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->workgroups = best_g;
+    b->unroll = best_u;
+    b->tuned_ms = best;
+    b->tuned = true;
+    return EBIC_OK;
+}
+
+// Packs per-run CBF pieces (offsets local to each piece) into the staging
+// buffers with global offsets.
+struct Packer {
+    ebic_batch *b;
+    int64_t cand = 0, cols = 0;
+    void add(const int32_t *off, const int32_t *c, int32_t P) {
+        const int32_t base = off[0];
+        for (int32_t i = 0; i < P; ++i) b->h_off[cand + i] = (int32_t)(cols + off[i] - base);
+        const int64_t n = off[P] - base;
+        std::copy(c + base, c + base + n, b->h_cols + cols);
+        cand += P;
+        cols += n;
+        b->h_off[cand] = (int32_t)cols;
+    }
+};
+
+template <typename F>
+void parallel_for(int32_t n, int32_t threads, F &&f) {
+    threads = std::max(1, std::min(threads, n));
+    if (threads == 1) {
+        for (int32_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int32_t> next{0};
+    std::vector<std::thread> pool;
+    for (int32_t t = 0; t < threads; ++t)
+        pool.emplace_back([&] {
+            for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (auto &th : pool) th.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, const int64_t *n_rows,
+                              const int32_t *n_cols, int32_t device, ebic_batch **out) {
+    if (!out || n_runs < 1 || !matrices || !n_rows || !n_cols)
+        return bfail(EBIC_E_ARG, "need n_runs >= 1 and non-null arrays");
+    *out = nullptr;
+    std::unique_ptr<ebic_batch> b(new (std::nothrow) ebic_batch());
+    if (!b) return bfail(EBIC_E_NOMEM, "cannot allocate batch");
+    b->device = device;
+    auto cleanup = [&](ebic_status st) {
+        ebic_batch_destroy(b.release());
+        return st;
+    };
+    for (int32_t r = 0; r < n_runs; ++r) {
+        ebic_ctx *c = nullptr;
+        ebic_status st = ebic_create(matrices[r], n_rows[r], n_cols[r], n_cols[r], EBIC_ROW_MAJOR,
+                                     device, &c);
+        if (st != EBIC_OK) return cleanup(st);
+        b->ctx.push_back(c);
+        st = ensure_index(c);
+        if (st != EBIC_OK) {
+            set_thread_error(c->err.c_str());
+            return cleanup(st);
+        }
+    }
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(bhip(e, "batch stream"));
+    if ((e = hipMalloc((void **)&b->d_runs, sizeof(IndexRun) * (size_t)n_runs)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_tile_base, sizeof(uint32_t) * ((size_t)n_runs + 1))) !=
+            hipSuccess ||
+        (e = hipMalloc((void **)&b->d_work, sizeof(unsigned int) * 2)) != hipSuccess ||
+        (e = hipMemset(b->d_work, 0, sizeof(unsigned int) * 2)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_runs, sizeof(IndexRun) * (size_t)n_runs,
+                           hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_tile_base, sizeof(uint32_t) * ((size_t)n_runs + 1),
+                           hipHostMallocDefault)) != hipSuccess)
+        return cleanup(bhip(e, "batch buffers"));
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) !=
+        hipSuccess)
+        return cleanup(bhip(e, "hipDeviceGetAttribute"));
+    b->resident_wgs = std::max(1, cus * batch_wgs_per_cu());
+    b->workgroups = b->resident_wgs;
+    *out = b.release();
+    return EBIC_OK;
+}
+
+ebic_status ebic_batch_destroy(ebic_batch *b) {
+    if (!b) return EBIC_OK;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    void *dev[] = {b->d_runs, b->d_tile_base, b->d_work, b->d_off, b->d_cols, b->d_counts,
+                   b->d_fit, b->d_acc, b->d_masks};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *host[] = {b->h_runs, b->h_tile_base, b->h_off, b->h_cols, b->h_counts, b->h_fit};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    for (ebic_ctx *c : b->ctx) ebic_destroy(c);
+    delete b;
+    return EBIC_OK;
+}
+
+ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
+    if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
+        return bfail(EBIC_E_ARG, "null argument or struct_size too small");
+    t->workgroups = b->workgroups;
+    t->unroll = b->unroll;
+    t->best_ms = b->tuned ? b->tuned_ms : 0.0;
+    return EBIC_OK;
+}
+
+ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t) {
+    if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
+        return bfail(EBIC_E_ARG, "null argument or struct_size too small");
+    if (t->workgroups < 0 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8))
+        return bfail(EBIC_E_ARG, "workgroups must be >= 0 and unroll 2, 4 or 8");
+    b->workgroups = t->workgroups ? t->workgroups : b->resident_wgs;
+    b->unroll = t->unroll;
+    b->tuned = true;
+    b->tuned_ms = 0.0;
+    return EBIC_OK;
+}
+
+ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
+                                const int32_t *const *cols, const int32_t *P,
+                                const ebic_params *params, uint64_t *const *masks,
+                                int32_t *const *counts, double *const *fitness, int32_t tune_now) {
+    if (!b || !offsets || !cols || !P || !params || !counts || !fitness)
+        return bfail(EBIC_E_ARG, "null argument");
+    if (params->struct_size < sizeof(ebic_params)) return bfail(EBIC_E_ARG, "params struct_size");
+    if (params->sigma < 0 || params->max_violations < 0)
+        return bfail(EBIC_E_RANGE, "sigma and max_violations must be >= 0");
+    if (params->max_violations > kIndexMaxViolations)
+        return bfail(EBIC_E_ARG, "batched evaluation supports max_violations <= 3");
+    if (params->want_masks && !masks) return bfail(EBIC_E_ARG, "want_masks needs masks");
+    const int32_t R = (int32_t)b->ctx.size();
+    Request q;
+    q.params = params;
+    q.masks = params->want_masks != 0;
+    q.P.assign((size_t)R, 0);
+    int64_t n_cols = 0, n_mask = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        if (P[r] < 0) return bfail(EBIC_E_ARG, "P must be >= 0");
+        if (P[r] == 0) continue;
+        ebic_ctx *c = b->ctx[(size_t)r];
+        if (!offsets[r] || !cols[r] || !counts[r] || !fitness[r] || (q.masks && !masks[r]))
+            return bfail(EBIC_E_ARG, "null per-run array");
+        ebic_status st;
+        if (!valid_cbf(c, offsets[r], cols[r], P[r], &st)) {
+            set_thread_error(("run " + std::to_string(r) + ": " + c->err).c_str());
+            return st;
+        }
+        if ((int64_t)P[r] * c->W > (int64_t(1) << 32) - 256)
+            return bfail(EBIC_E_ARG, "population too large for one launch");
+        q.P[(size_t)r] = P[r];
+        q.n_cand += P[r];
+        n_cols += offsets[r][P[r]];
+        if (q.masks) n_mask += (int64_t)P[r] * 2 * c->W;
+    }
+    q.n_cols = n_cols;
+    if (q.n_cand == 0) return EBIC_OK;
+    BHIP(hipSetDevice(b->device));
+    ebic_status st = reserve(b, q.n_cand, n_cols, n_mask);
+    if (st != EBIC_OK) return st;
+    Packer pk{b};
+    b->h_off[0] = 0;
+    for (int32_t r = 0; r < R; ++r)
+        if (q.P[(size_t)r]) pk.add(offsets[r], cols[r], q.P[(size_t)r]);
+    if (tune_now && (st = tune(b, q)) != EBIC_OK) return st;
+    if ((st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+    int64_t cand = 0, mw = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t n = q.P[(size_t)r];
+        if (!n) continue;
+        std::copy(b->h_counts + cand, b->h_counts + cand + n, counts[r]);
+        std::copy(b->h_fit + cand, b->h_fit + cand + n, fitness[r]);
+        if (q.masks) {
+            const int64_t words = (int64_t)n * 2 * b->ctx[(size_t)r]->W;
+            BHIP(hipMemcpy(masks[r], b->d_masks + mw, sizeof(uint64_t) * (size_t)words,
+                           hipMemcpyDeviceToHost));
+            mw += words;
+        }
+        cand += n;
+    }
+    return EBIC_OK;
+}
+
+ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t generations,
+                              const ebic_evolve_params *params,
+                              ebic_batch_generation_fn on_generation, void *user,
+                              int32_t host_threads, ebic_result **results) {
+    if (!b || !seeds || !params || !results) return bfail(EBIC_E_ARG, "null argument");
+    if (generations < 0) return bfail(EBIC_E_ARG, "generations must be >= 0");
+    const int32_t R = (int32_t)b->ctx.size();
+    for (int32_t r = 0; r < R; ++r) {
+        ebic_status st = check_params(params, b->ctx[(size_t)r]->n, b->ctx[(size_t)r]->m);
+        if (st != EBIC_OK) return st;
+    }
+    if (params->eval.max_violations > kIndexMaxViolations ||
+        params->expand.max_violations > kIndexMaxViolations)
+        return bfail(EBIC_E_ARG, "batched runs support max_violations <= 3");
+    if (host_threads <= 0) host_threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
+    BHIP(hipSetDevice(b->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    double eval_ms = 0.0;
+    int64_t evaluated = 0;
+
+    // Per-run parameters: the library calls each run's on_generation with a
+    // trampoline that adds the run index and serialises the user callback.
+    struct Tramp {
+        ebic_batch_generation_fn fn;
+        void *user;
+        int32_t run;
+        std::mutex *mu;
+    };
+    std::mutex mu;
+    std::vector<Tramp> tramps((size_t)R);
+    std::vector<ebic_evolve_params> rp((size_t)R, *params);
+    std::vector<std::unique_ptr<Run>> runs;
+    for (int32_t r = 0; r < R; ++r) {
+        tramps[(size_t)r] = Tramp{on_generation, user, r, &mu};
+        rp[(size_t)r].on_generation =
+            on_generation ? +[](void *u, int32_t gen, const int32_t *off, const int32_t *cols,
+                                int32_t P, const int32_t *cnt, const double *fit) {
+                auto *t = static_cast<Tramp *>(u);
+                std::lock_guard<std::mutex> lk(*t->mu);
+                t->fn(t->user, t->run, gen, off, cols, P, cnt, fit);
+            }
+                          : nullptr;
+        rp[(size_t)r].user = &tramps[(size_t)r];
+        runs.emplace_back(new Run(b->ctx[(size_t)r]->m, seeds[r], generations, rp[(size_t)r]));
+    }
+    std::vector<uint8_t> active((size_t)R, 1);
+    bool first = true;
+    for (;;) {
+        parallel_for(R, host_threads, [&](int32_t r) {
+            if (active[(size_t)r]) active[(size_t)r] = runs[(size_t)r]->next() ? 1 : 0;
+        });
+        Request q;
+        q.params = &runs[0]->eval_params();
+        q.P.assign((size_t)R, 0);
+        int64_t n_cols = 0;
+        for (int32_t r = 0; r < R; ++r)
+            if (active[(size_t)r]) {
+                const Pop &pop = runs[(size_t)r]->pending();
+                const int32_t f = runs[(size_t)r]->first_new();
+                q.P[(size_t)r] = pop.size() - f;
+                q.n_cand += q.P[(size_t)r];
+                n_cols += pop.off.back() - pop.off[(size_t)f];
+            }
+        if (q.n_cand == 0) break;
+        q.n_cols = n_cols;
+        ebic_status st = reserve(b, q.n_cand, n_cols, 0);
+        if (st != EBIC_OK) return st;
+        Packer pk{b};
+        b->h_off[0] = 0;
+        for (int32_t r = 0; r < R; ++r)
+            if (q.P[(size_t)r]) {
+                const Pop &pop = runs[(size_t)r]->pending();
+                const int32_t f = runs[(size_t)r]->first_new();
+                pk.add(pop.off.data() + f, pop.cols.data(), q.P[(size_t)r]);
+            }
+        if (first && !b->tuned && (st = tune(b, q)) != EBIC_OK) return st;
+        first = false;
+        const auto e0 = std::chrono::steady_clock::now();
+        if ((st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+        eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
+        evaluated += q.n_cand;
+        std::vector<int64_t> base((size_t)R + 1, 0);
+        for (int32_t r = 0; r < R; ++r) base[(size_t)r + 1] = base[(size_t)r] + q.P[(size_t)r];
+        parallel_for(R, host_threads, [&](int32_t r) {
+            if (q.P[(size_t)r])
+                runs[(size_t)r]->accept(b->h_counts + base[(size_t)r], b->h_fit + base[(size_t)r]);
+        });
+    }
+
+    // Steps 6-7 for every run in one launch, with masks.
+    ebic_params ex = params->expand;
+    ex.want_masks = 1;
+    Request q;
+    q.params = &ex;
+    q.masks = true;
+    q.P.assign((size_t)R, 0);
+    int64_t n_cols = 0, n_mask = 0;
+    std::vector<Pop> tops((size_t)R);
+    for (int32_t r = 0; r < R; ++r) {
+        for (const TopEntry &e : runs[(size_t)r]->top()) tops[(size_t)r].push(e.s.data(), (int32_t)e.s.size());
+        q.P[(size_t)r] = tops[(size_t)r].size();
+        q.n_cand += q.P[(size_t)r];
+        n_cols += tops[(size_t)r].off.back();
+        n_mask += (int64_t)q.P[(size_t)r] * 2 * b->ctx[(size_t)r]->W;
+    }
+    q.n_cols = n_cols;
+    ebic_status st = reserve(b, std::max<int64_t>(q.n_cand, 1), n_cols, std::max<int64_t>(n_mask, 1));
+    if (st != EBIC_OK) return st;
+    Packer pk{b};
+    b->h_off[0] = 0;
+    for (int32_t r = 0; r < R; ++r)
+        if (q.P[(size_t)r]) pk.add(tops[(size_t)r].off.data(), tops[(size_t)r].cols.data(), q.P[(size_t)r]);
+    const auto e0 = std::chrono::steady_clock::now();
+    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+    std::vector<uint64_t> all_masks((size_t)std::max<int64_t>(n_mask, 1));
+    if (n_mask)
+        BHIP(hipMemcpy(all_masks.data(), b->d_masks, sizeof(uint64_t) * (size_t)n_mask,
+                       hipMemcpyDeviceToHost));
+    eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
+    evaluated += q.n_cand;
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int64_t cand = 0, mw = 0;
+    std::vector<ebic_result *> out((size_t)R, nullptr);
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t K = q.P[(size_t)r];
+        const int64_t W = b->ctx[(size_t)r]->W;
+        std::vector<uint64_t> m(all_masks.begin() + mw, all_masks.begin() + mw + (int64_t)K * 2 * W);
+        std::vector<int32_t> rc(b->h_counts + cand, b->h_counts + cand + K);
+        std::vector<double> rf(b->h_fit + cand, b->h_fit + cand + K);
+        out[(size_t)r] = make_result(runs[(size_t)r]->top(), W, m, std::move(rc), std::move(rf));
+        if (!out[(size_t)r]) {
+            for (ebic_result *x : out) ebic_result_free(x);
+            return bfail(EBIC_E_NOMEM, "cannot allocate results");
+        }
+        ebic_run_stats &s = out[(size_t)r]->stats;
+        s.struct_size = sizeof(ebic_run_stats);
+        s.generations_run = runs[(size_t)r]->generations_run();
+        s.stopped_by_tabu = runs[(size_t)r]->stopped() ? 1 : 0;
+        s.candidates_evaluated = evaluated;     // whole batch
+        s.wall_ms = wall;                       // whole batch
+        s.eval_ms = eval_ms;
+        s.host_ms = wall - eval_ms;
+        cand += K;
+        mw += (int64_t)K * 2 * W;
+    }
+    for (int32_t r = 0; r < R; ++r) results[r] = out[(size_t)r];
+    return EBIC_OK;
+}
+
+}  // extern "C"

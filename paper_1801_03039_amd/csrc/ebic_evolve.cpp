@@ -20,111 +20,11 @@
 #include <unordered_set>
 #include <vector>
 
-#include "../../include/ebic.h"
-
-namespace ebic {
-// Message for ebic_last_error(NULL) (defined with the runtime).
-void set_thread_error(const char *msg);
-}  // namespace ebic
+#include "ebic_run.h"
 
 namespace {
 
-// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): Weyl step
-// 0x9E3779B97F4A7C15 and the 64-bit mixing finalizer.
-struct SplitMix64 {
-    uint64_t s;
-    explicit SplitMix64(uint64_t seed) : s(seed) {}
-    uint64_t next() {
-        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    }
-    // Draw in [0, n): plain modulo (the documented reading).
-    uint32_t below(uint64_t n) { return (uint32_t)(next() % n); }
-};
-
-// A population in CBF form.
-struct Pop {
-    std::vector<int32_t> off{0};
-    std::vector<int32_t> cols;
-    std::vector<int32_t> counts;
-    std::vector<double> fit;
-    int32_t size() const { return (int32_t)off.size() - 1; }
-    const int32_t *series(int32_t i) const { return cols.data() + off[(size_t)i]; }
-    int32_t len(int32_t i) const { return off[(size_t)i + 1] - off[(size_t)i]; }
-    void clear() {
-        off.assign(1, 0);
-        cols.clear();
-        counts.clear();
-        fit.clear();
-    }
-    void push(const int32_t *s, int32_t L) {
-        cols.insert(cols.end(), s, s + L);
-        off.push_back((int32_t)cols.size());
-    }
-};
-
-// Tabu list: every series ever analysed, exact and ordered.  Series live in
-// an append-only arena; the set holds (offset, length) keys into it.
-class Tabu {
-  public:
-    Tabu() : set_(1024, Hash{&arena_}, Eq{&arena_}) {}
-    bool contains(const int32_t *s, int32_t L) {
-        const size_t at = stage(s, L);
-        const bool hit = set_.find(Key{at, L}) != set_.end();
-        arena_.resize(at);
-        return hit;
-    }
-    // Inserts; returns false when already present.
-    bool insert(const int32_t *s, int32_t L) {
-        const size_t at = stage(s, L);
-        if (!set_.insert(Key{at, L}).second) {
-            arena_.resize(at);
-            return false;
-        }
-        return true;
-    }
-
-  private:
-    struct Key {
-        size_t at;
-        int32_t len;
-    };
-    struct Hash {
-        const std::vector<int32_t> *a;
-        size_t operator()(const Key &k) const {
-            uint64_t h = 0x84222325cbf29ce4ull ^ (uint64_t)k.len;
-            const int32_t *p = a->data() + k.at;
-            for (int32_t i = 0; i < k.len; ++i) {
-                h ^= (uint32_t)p[i];
-                h *= 0x100000001b3ull;
-                h ^= h >> 29;
-            }
-            return (size_t)h;
-        }
-    };
-    struct Eq {
-        const std::vector<int32_t> *a;
-        bool operator()(const Key &x, const Key &y) const {
-            return x.len == y.len &&
-                   std::memcmp(a->data() + x.at, a->data() + y.at, sizeof(int32_t) * x.len) == 0;
-        }
-    };
-    size_t stage(const int32_t *s, int32_t L) {
-        const size_t at = arena_.size();
-        arena_.insert(arena_.end(), s, s + L);
-        return at;
-    }
-    std::vector<int32_t> arena_;
-    std::unordered_set<Key, Hash, Eq> set_;
-};
-
-struct TopEntry {
-    std::vector<int32_t> s;
-    int32_t count;
-    double fit;
-};
+using namespace ebic::host;
 
 using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t0) {
@@ -152,387 +52,47 @@ struct Evaluator {
     }
 };
 
-// Step 5: the top-rank list update.
-//
-// Members are visited by decreasing fitness (stable).  A member is skipped
-// when its fitness is not positive or its series is already listed; it is
-// rejected when a listed entry of at least its fitness overlaps it by more
-// than theta (|x & e| / min(|x|, |e|) on column sets); otherwise it evicts
-// the weaker entries it overlaps by more than theta and joins the list.  The
-// list is then sorted by fitness (stable) and cut to K.
-//
-// Only entries sharing a column with x can overlap it (or equal it), so the
-// intersections are accumulated through a column -> entries index instead of
-// comparing x with every entry; the decisions are the same.
-//
-// The pass also stops as soon as its outcome is fixed.  An entry can only be
-// evicted by a strictly fitter member, and members come by decreasing
-// fitness; so when x is reached, every live entry with fitness >= f(x) stays
-// live to the end and precedes x (and everything after x) in the final
-// stable order.  Once there are K of them, no later member can enter the
-// final K or remove one of them, and whatever it evicts has fitness < f(x)
-// and falls beyond the cut anyway.
-class TopRank {
-  public:
-    explicit TopRank(int32_t n_cols) : by_col_((size_t)n_cols) {}
 
-    const std::vector<TopEntry> &entries() const { return top_; }
-
-    void update(const Pop &pop, double theta, int32_t K) {
-        const int32_t P = pop.size();
-        order_.resize((size_t)P);
-        for (int32_t i = 0; i < P; ++i) order_[(size_t)i] = i;
-        std::stable_sort(order_.begin(), order_.end(), [&](int32_t a, int32_t b) {
-            return pop.fit[(size_t)a] > pop.fit[(size_t)b];
-        });
-        // working list: top_ in insertion order, plus liveness and the index
-        alive_.assign(top_.size(), 1);
-        for (auto &v : by_col_) v.clear();
-        for (size_t e = 0; e < top_.size(); ++e)
-            for (int32_t c : top_[e].s) by_col_[(size_t)c].push_back((int32_t)e);
-
-        const size_t n_old = top_.size();  // sorted by decreasing fitness
-        size_t old_ptr = 0;
-        int32_t settled = 0;                // live entries with fitness >= f(x)
-        for (int32_t i : order_) {
-            const double fx = pop.fit[(size_t)i];
-            if (!(fx > 0.0)) break;         // the rest are not positive either
-            for (; old_ptr < n_old && top_[old_ptr].fit >= fx; ++old_ptr)
-                settled += alive_[old_ptr];
-            if (settled >= K) break;
-            const int32_t *x = pop.series(i);
-            const int32_t lx = pop.len(i);
-            // intersections with every entry sharing a column with x
-            touched_.clear();
-            if (inter_.size() < top_.size()) inter_.resize(top_.size(), 0);
-            for (int32_t t = 0; t < lx; ++t)
-                for (int32_t e : by_col_[(size_t)x[t]]) {
-                    if (!alive_[(size_t)e]) continue;
-                    if (inter_[(size_t)e]++ == 0) touched_.push_back(e);
-                }
-            bool listed = false, blocked = false;
-            for (int32_t e : touched_) {
-                const TopEntry &te = top_[(size_t)e];
-                const int32_t le = (int32_t)te.s.size();
-                if (inter_[(size_t)e] == lx && le == lx && std::equal(te.s.begin(), te.s.end(), x))
-                    listed = true;
-            }
-            if (!listed)
-                for (int32_t e : touched_) {
-                    const TopEntry &te = top_[(size_t)e];
-                    const double ov = (double)inter_[(size_t)e] /
-                                      (double)std::min(lx, (int32_t)te.s.size());
-                    if (te.fit >= fx && ov > theta) {
-                        blocked = true;
-                        break;
-                    }
-                }
-            if (!listed && !blocked) {
-                for (int32_t e : touched_) {
-                    const TopEntry &te = top_[(size_t)e];
-                    const double ov = (double)inter_[(size_t)e] /
-                                      (double)std::min(lx, (int32_t)te.s.size());
-                    if (te.fit < fx && ov > theta) alive_[(size_t)e] = 0;
-                }
-                const int32_t id = (int32_t)top_.size();
-                top_.push_back(TopEntry{std::vector<int32_t>(x, x + lx), pop.counts[(size_t)i], fx});
-                alive_.push_back(1);
-                ++settled;                  // f(x) >= the fitness of every later member
-                for (int32_t t = 0; t < lx; ++t) by_col_[(size_t)x[t]].push_back(id);
-            }
-            for (int32_t e : touched_) inter_[(size_t)e] = 0;
-        }
-        // compact (insertion order kept), stable sort by fitness, cut to K
-        size_t k = 0;
-        for (size_t e = 0; e < top_.size(); ++e)
-            if (alive_[e]) {
-                if (k != e) top_[k] = std::move(top_[e]);
-                ++k;
-            }
-        top_.resize(k);
-        std::stable_sort(top_.begin(), top_.end(),
-                         [](const TopEntry &a, const TopEntry &b) { return a.fit > b.fit; });
-        if ((int32_t)top_.size() > K) top_.resize((size_t)K);
-    }
-
-  private:
-    std::vector<TopEntry> top_;
-    std::vector<std::vector<int32_t>> by_col_;
-    std::vector<uint8_t> alive_;
-    std::vector<int32_t> inter_, touched_, order_;
-};
-
-bool contains(const std::vector<int32_t> &s, int32_t c) {
-    return std::find(s.begin(), s.end(), c) != s.end();
-}
-
-int32_t new_column(SplitMix64 &rng, const std::vector<int32_t> &s, int32_t M) {
-    for (;;) {
-        const int32_t c = (int32_t)rng.below((uint64_t)M);
-        if (!contains(s, c)) return c;
-    }
-}
-
-enum { OP_INSERT = 0, OP_DELETE, OP_SWAP, OP_SUBSTITUTE, OP_CROSSOVER };
-
-// Mutations of Fig. 1a-d; inapplicable ones leave s unchanged and draw nothing.
-void mutate(SplitMix64 &rng, std::vector<int32_t> &s, int op, const ebic_evolve_params &p,
-            int32_t M) {
-    const int32_t L = (int32_t)s.size();
-    switch (op) {
-    case OP_INSERT:
-        if (L < p.len_max) {
-            const int32_t pos = (int32_t)rng.below((uint64_t)L + 1);
-            const int32_t c = new_column(rng, s, M);
-            s.insert(s.begin() + pos, c);
-        }
-        break;
-    case OP_DELETE:
-        if (L > p.len_min) s.erase(s.begin() + rng.below((uint64_t)L));
-        break;
-    case OP_SWAP:
-        if (L >= 2) {
-            const int32_t i = (int32_t)rng.below((uint64_t)L);
-            int32_t j = (int32_t)rng.below((uint64_t)L - 1);
-            if (j >= i) ++j;
-            std::swap(s[(size_t)i], s[(size_t)j]);
-        }
-        break;
-    case OP_SUBSTITUTE:
-        if (L < M) {
-            const int32_t pos = (int32_t)rng.below((uint64_t)L);
-            s[(size_t)pos] = new_column(rng, s, M);
-        }
-        break;
-    default:
-        break;
-    }
-}
-
-// One-point crossover of Fig. 1e with duplicate removal and clamping.
-void crossover(SplitMix64 &rng, const int32_t *a, int32_t la, const int32_t *b, int32_t lb,
-               const ebic_evolve_params &p, std::vector<int32_t> &child) {
-    const int32_t i = 1 + (int32_t)rng.below((uint64_t)la);
-    const int32_t j = (int32_t)rng.below((uint64_t)lb);
-    child.assign(a, a + i);
-    for (int32_t t = j; t < lb; ++t) {
-        const int32_t c = b[t];
-        if (std::find(a, a + i, c) == a + i) child.push_back(c);
-    }
-    if ((int32_t)child.size() > p.len_max) child.resize((size_t)p.len_max);
-    if ((int32_t)child.size() < p.len_min) child.assign(a, a + la);
-}
-
-// Number of ordered series of distinct columns with lengths in
-// [lmin, lmax], saturated at 2^62.
-int64_t search_space(int32_t M, int32_t lmin, int32_t lmax) {
-    const int64_t cap = int64_t(1) << 62;
-    int64_t total = 0;
-    for (int32_t L = lmin; L <= lmax; ++L) {
-        int64_t t = 1;
-        for (int32_t i = 0; i < L && t < cap; ++i) {
-            const int64_t f = (int64_t)M - i;
-            t = (f > 0 && t > cap / f) ? cap : t * f;
-        }
-        total = (t >= cap - total) ? cap : total + t;
-    }
-    return total;
-}
-
-ebic_status evolve_error(ebic_status st, const char *msg) {
-    ebic::set_thread_error(msg);
-    return st;
-}
 
 }  // namespace
 
-struct ebic_result {
-    std::vector<std::vector<int32_t>> cols;
-    std::vector<int32_t> counts;
-    std::vector<double> fit;
-    std::vector<std::vector<uint64_t>> masks;
-    ebic_run_stats stats{};
-};
-
 namespace {
-
-ebic_status check_params(const ebic_evolve_params *p, int64_t n_rows, int32_t M) {
-    if (!p || p->struct_size < sizeof(ebic_evolve_params))
-        return evolve_error(EBIC_E_ARG, "params is null or struct_size too small");
-    if (n_rows < 1 || M < 1) return evolve_error(EBIC_E_ARG, "empty matrix");
-    if (p->population < 1 || p->len_min < 1 || p->len_min > p->len_max || p->len_max > M)
-        return evolve_error(EBIC_E_ARG, "need P >= 1 and 1 <= len_min <= len_max <= n_cols");
-    if (p->tournament < 1) return evolve_error(EBIC_E_ARG, "tournament must be >= 1");
-    int64_t wsum = 0;
-    for (int i = 0; i < 5; ++i) {
-        if (p->op_weight[i] < 0) return evolve_error(EBIC_E_ARG, "negative operation weight");
-        wsum += p->op_weight[i];
-    }
-    if (wsum <= 0) return evolve_error(EBIC_E_ARG, "operation weights sum to 0");
-    if (p->elite_den < 1 || p->elite_num < 0 || p->elite_num > p->elite_den)
-        return evolve_error(EBIC_E_ARG, "need 0 <= elite_num <= elite_den, elite_den >= 1");
-    if (p->toplist_size < 1) return evolve_error(EBIC_E_ARG, "toplist_size must be >= 1");
-    if (!(p->penalty_base > 0.0) || !(p->overlap >= 0.0 && p->overlap <= 1.0))
-        return evolve_error(EBIC_E_ARG, "need penalty_base > 0 and 0 <= overlap <= 1");
-    if (p->eval.struct_size < sizeof(ebic_params) || p->expand.struct_size < sizeof(ebic_params))
-        return evolve_error(EBIC_E_ARG, "eval/expand struct_size too small");
-    if (p->eval.sigma < 0 || p->eval.max_violations < 0 || p->expand.sigma < 0 ||
-        p->expand.max_violations < 0)
-        return evolve_error(EBIC_E_RANGE, "sigma and max_violations must be >= 0");
-    if ((int64_t)p->population > search_space(M, p->len_min, p->len_max))
-        return evolve_error(EBIC_E_ARG, "population exceeds the number of distinct series");
-    return EBIC_OK;
-}
 
 ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t generations,
                 const ebic_evolve_params &p, ebic_result **out) {
     const auto t_start = Clock::now();
-    const int32_t P = p.population;
-    const int32_t tabu_limit = p.tabu_limit < 0 ? P : p.tabu_limit;
     const int64_t W = (n_rows + 63) / 64;
-    SplitMix64 rng(seed);
-    Tabu tabu;
-    TopRank toprank(M);
-    ebic_params evalp = p.eval;
-    evalp.want_masks = 0;
-
-    auto emit = [&](int32_t g, const Pop &pop) {
-        if (p.on_generation)
-            p.on_generation(p.user, g, pop.off.data(), pop.cols.data(), pop.size(),
-                            pop.counts.data(), pop.fit.data());
-    };
-
-    // Step 1: initial population.
-    Pop prev, cur;
-    std::vector<int32_t> s;
-    while (prev.size() < P) {
-        const int32_t L = p.len_min + (int32_t)rng.below((uint64_t)(p.len_max - p.len_min + 1));
-        s.clear();
-        while ((int32_t)s.size() < L) {
-            const int32_t c = (int32_t)rng.below((uint64_t)M);
-            if (!contains(s, c)) s.push_back(c);
-        }
-        if (!tabu.insert(s.data(), L)) continue;
-        prev.push(s.data(), L);
-    }
-    prev.counts.resize((size_t)P);
-    prev.fit.resize((size_t)P);
-    ebic_status st = ev(prev, 0, &evalp, nullptr, prev.counts.data(), prev.fit.data());
-    if (st != EBIC_OK) return st;
-    emit(0, prev);
-    toprank.update(prev, p.overlap, p.toplist_size);
-    const std::vector<TopEntry> &top = toprank.entries();
-
-    int64_t wsum = 0;
-    for (int i = 0; i < 5; ++i) wsum += p.op_weight[i];
-    std::vector<int32_t> penalty((size_t)M);
-    std::vector<int32_t> child;
-    int32_t gens_run = 0;
-    bool stopped = false;
-
-    auto tournament = [&]() -> int32_t {
-        int32_t best = -1;
-        double best_adj = -INFINITY;
-        for (int32_t r = 0; r < p.tournament; ++r) {
-            const int32_t i = (int32_t)rng.below((uint64_t)prev.size());
-            const int32_t *si = prev.series(i);
-            const int32_t L = prev.len(i);
-            int64_t sum = 0;
-            for (int32_t t = 0; t < L; ++t) sum += penalty[(size_t)si[t]];
-            const double vartheta = (double)sum / (double)L;
-            const double adj = prev.fit[(size_t)i] / std::pow(p.penalty_base, vartheta);
-            if (adj > best_adj) {
-                best = i;
-                best_adj = adj;
-            }
-        }
-        return best;
-    };
-
-    for (int32_t g = 1; g <= generations; ++g) {
-        // Step 2: elitism and column penalties.
-        std::fill(penalty.begin(), penalty.end(), 0);
-        cur.clear();
-        const int32_t n_e =
-            (int32_t)std::min<int64_t>((int64_t)top.size(), (int64_t)P * p.elite_num / p.elite_den);
-        for (int32_t e = 0; e < n_e; ++e) {
-            const TopEntry &te = top[(size_t)e];
-            cur.push(te.s.data(), (int32_t)te.s.size());
-            cur.counts.push_back(te.count);
-            cur.fit.push_back(te.fit);
-            for (int32_t c : te.s) ++penalty[(size_t)c];
-        }
-        // Step 3: fill with novel children.
-        int32_t hits = 0;
-        while (cur.size() < P) {
-            const int32_t ia = tournament();
-            const uint64_t u = rng.below((uint64_t)wsum);
-            int op = 0;
-            int64_t acc = 0;
-            for (op = 0; op < 5; ++op) {
-                acc += p.op_weight[op];
-                if ((int64_t)u < acc) break;
-            }
-            if (op == OP_CROSSOVER) {
-                const int32_t ib = tournament();
-                crossover(rng, prev.series(ia), prev.len(ia), prev.series(ib), prev.len(ib), p,
-                          child);
-            } else {
-                child.assign(prev.series(ia), prev.series(ia) + prev.len(ia));
-                mutate(rng, child, op, p, M);
-            }
-            const int32_t L = (int32_t)child.size();
-            if (!tabu.insert(child.data(), L)) {
-                if (++hits > tabu_limit) {
-                    stopped = true;
-                    break;
-                }
-                continue;
-            }
-            cur.push(child.data(), L);
-            for (int32_t c : child) ++penalty[(size_t)c];
-        }
-        if (stopped) break;
-        // Step 4: evaluate the new members.
-        cur.counts.resize((size_t)P);
-        cur.fit.resize((size_t)P);
-        st = ev(cur, n_e, &evalp, nullptr, cur.counts.data() + n_e, cur.fit.data() + n_e);
+    Run run(M, seed, generations, p);
+    std::vector<int32_t> cnt;
+    std::vector<double> fit;
+    while (run.next()) {
+        const Pop &pop = run.pending();
+        const int32_t first = run.first_new();
+        cnt.resize((size_t)(pop.size() - first));
+        fit.resize(cnt.size());
+        ebic_status st = ev(pop, first, &run.eval_params(), nullptr, cnt.data(), fit.data());
         if (st != EBIC_OK) return st;
-        emit(g, cur);
-        gens_run = g;
-        // Step 5: top-rank list.
-        toprank.update(cur, p.overlap, p.toplist_size);
-        std::swap(prev, cur);
+        run.accept(cnt.data(), fit.data());
     }
-
     // Steps 6-7: rows of the listed series with the expansion parameters.
-    ebic_result *r = new (std::nothrow) ebic_result();
-    if (!r) return evolve_error(EBIC_E_NOMEM, "cannot allocate result");
-    if (!top.empty()) {
+    const std::vector<TopEntry> &top = run.top();
+    const int32_t K = (int32_t)top.size();
+    std::vector<uint64_t> masks((size_t)K * 2 * (size_t)W);
+    std::vector<int32_t> rc((size_t)K);
+    std::vector<double> rf((size_t)K);
+    if (K > 0) {
         Pop tp;
         for (const TopEntry &e : top) tp.push(e.s.data(), (int32_t)e.s.size());
-        const int32_t K = tp.size();
-        std::vector<uint64_t> masks((size_t)K * 2 * (size_t)W);
-        r->counts.resize((size_t)K);
-        r->fit.resize((size_t)K);
         ebic_params ex = p.expand;
         ex.want_masks = 1;
-        st = ev(tp, 0, &ex, masks.data(), r->counts.data(), r->fit.data());
-        if (st != EBIC_OK) {
-            delete r;
-            return st;
-        }
-        for (int32_t i = 0; i < K; ++i) {
-            r->cols.push_back(top[(size_t)i].s);
-            std::vector<uint64_t> m((size_t)W);
-            for (int64_t w = 0; w < W; ++w)
-                m[(size_t)w] = masks[((size_t)i * 2 + 0) * W + w] | masks[((size_t)i * 2 + 1) * W + w];
-            r->masks.push_back(std::move(m));
-        }
+        ebic_status st = ev(tp, 0, &ex, masks.data(), rc.data(), rf.data());
+        if (st != EBIC_OK) return st;
     }
+    ebic_result *r = make_result(top, W, masks, std::move(rc), std::move(rf));
+    if (!r) return evolve_error(EBIC_E_NOMEM, "cannot allocate result");
     r->stats.struct_size = sizeof(ebic_run_stats);
-    r->stats.generations_run = gens_run;
-    r->stats.stopped_by_tabu = stopped ? 1 : 0;
+    r->stats.generations_run = run.generations_run();
+    r->stats.stopped_by_tabu = run.stopped() ? 1 : 0;
     r->stats.candidates_evaluated = ev.evaluated;
     r->stats.wall_ms = ms_since(t_start);
     r->stats.eval_ms = ev.ms;

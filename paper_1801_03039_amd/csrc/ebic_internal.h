@@ -48,6 +48,48 @@ struct EvalArgs {
     unsigned long long *acc;     // P zero-initialised packed accumulators; left zeroed
 };
 
+// One run's share of an index evaluation (device-visible POD).
+struct IndexRun {
+    const uint64_t *idx;     // pairwise order index of the run's matrix
+    const uint8_t *tie;      // its tie flags
+    const double *logt;      // ln table of the run's matrix
+    int64_t n, W, wpad;      // rows, mask words, padded words
+    int32_t m;               // columns
+    int32_t P;               // candidates of the run in this launch
+    int64_t cand_base;       // index of the run's first candidate in the launch
+    int64_t mask_base;       // first mask word of the run (when masks are written)
+};
+
+// A persistent multi-run launch.  runs/tile_base/work are device arrays;
+// tile_base[r] is the first tile of run r (tile_base[n_runs] = total);
+// work[2] is a zeroed queue state that the kernel leaves zeroed.
+struct BatchLaunch {
+    const IndexRun *runs;
+    const uint32_t *tile_base;
+    int32_t n_runs;
+    unsigned int *work;
+    const int32_t *offsets;
+    const int32_t *cols;
+    int64_t n_entries;
+    int32_t sigma, k, negative;
+    uint64_t *masks;
+    unsigned long long *acc;
+    int32_t *counts;
+    double *fitness;
+    uint32_t grid;     // persistent workgroups
+    int32_t unroll;    // pairs per batch of loads: 2, 4 or 8
+};
+
+hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream);
+// Workgroups of the batch kernel resident per compute unit.
+int batch_wgs_per_cu();
+
+// Runtime helpers shared with the multi-run driver (ebic_runtime.cpp).
+void set_thread_error(const char *msg);
+ebic_status ensure_index(ebic_ctx *ctx);  // builds the order index if missing
+bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
+               ebic_status *st);          // host CBF checks of ebic_evaluate
+
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               const EvalArgs &e, hipStream_t stream);
 

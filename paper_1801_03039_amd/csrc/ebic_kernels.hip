@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "ebic_internal.h"
 
@@ -30,6 +31,15 @@ constexpr int kBlock = 256;
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Pointers read from device memory (a run table) are generic to the
+// compiler; declaring them global lets it emit global (not flat) loads.
+template <typename T>
+using global_ptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(const T *p) {
+    return (global_ptr<T>)p;
+}
 
 __device__ __forceinline__ uint64_t tail_bits(int64_t n, int64_t w, int64_t W) {
     if (w < W - 1) return ~0ull;
@@ -151,9 +161,10 @@ __global__ __launch_bounds__(kBlock) void tie_flags_kernel(const uint64_t *__res
 constexpr int kShareShift = 33;
 constexpr uint64_t kBadBit = 1ull << 32;
 
+template <typename LogPtr>
 __device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, int64_t share,
                                             int64_t parts, int32_t L, int32_t sigma,
-                                            const double *__restrict__ logt,
+                                            LogPtr logt,
                                             unsigned long long *__restrict__ acc,
                                             int32_t *__restrict__ counts,
                                             double *__restrict__ fitness) {
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 // kUnroll pairs), and a lane stops once every row of its word is rejected in
 // every enabled direction.
 constexpr int kIdxLds = 4096;   // staged column entries per workgroup
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;   // pairs per batch of loads (single-run default)
 
 template <int K, bool NEG>
 __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1], uint64_t lt_pq,
@@ -300,113 +311,136 @@ __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1
     }
 }
 
-template <int K, bool NEG>
-__global__ __launch_bounds__(kBlock) void eval_index_kernel(
-    const uint64_t *__restrict__ idx, int64_t n, int32_t m, int64_t W, int64_t wpad,
-    const uint8_t *__restrict__ tie, const int32_t *__restrict__ offsets,
-    const int32_t *__restrict__ cols, int32_t P, int64_t n_entries, int32_t sigma,
-    const double *__restrict__ logt, uint64_t *__restrict__ masks,
-    unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
-    double *__restrict__ fitness) {
+// One tile (kBlock consecutive items) of one run.  Shared by the single-run
+// kernel (tile = workgroup) and the persistent multi-run kernel.
+template <int K, bool NEG, int U>
+__device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
+                                           const int32_t *__restrict__ offsets,
+                                           const int32_t *__restrict__ cols, int64_t n_entries,
+                                           int32_t sigma, uint64_t *__restrict__ masks,
+                                           unsigned long long *__restrict__ acc,
+                                           int32_t *__restrict__ counts,
+                                           double *__restrict__ fitness) {
     __shared__ int32_t s_cols[kIdxLds];
+    const auto idx = as_global(R.idx);
+    const auto tie = as_global(R.tie);
+    const auto logt = as_global(R.logt);
+    const int64_t n = R.n, W = R.W, wpad = R.wpad;
+    const int32_t m = R.m, P = R.P;
     const int tid = threadIdx.x, lane = tid & 63;
     // The launcher guarantees P * W < 2^32.
     const uint32_t Wu = (uint32_t)W;
-    const uint32_t item = blockIdx.x * (uint32_t)kBlock + (uint32_t)tid;
+    const uint32_t item = tile * (uint32_t)kBlock + (uint32_t)tid;
     const uint32_t total = (uint32_t)P * Wu;
     const bool active = item < total;
-    const uint32_t c = active ? item / Wu : (uint32_t)P - 1;
-    const uint32_t w = active ? item - c * Wu : 0;
-
-    // Stage the columns of candidates [c_lo, c_hi] (uniform decision).
-    const uint32_t i0 = blockIdx.x * (uint32_t)kBlock;
-    const uint32_t c_lo = i0 / Wu;
-    const uint32_t c_hi = min((i0 + kBlock - 1) / Wu, (uint32_t)P - 1);
-    const int64_t b0 = offsets[c_lo], b1 = offsets[c_hi + 1];
-    const bool staged = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
-    if (staged) {
-        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += kBlock) s_cols[e] = cols[b0 + e];
-        __syncthreads();
-    }
+    const uint32_t cl = active ? item / Wu : (uint32_t)P - 1;   // candidate within the run
+    const uint32_t w = active ? item - cl * Wu : 0;
+    const int64_t c = R.cand_base + cl;                          // candidate in the launch
 
     const int64_t start = offsets[c], end = offsets[c + 1];
     const bool ok_range = start >= 0 && end <= n_entries && end > start;
     const int32_t L = ok_range ? (int32_t)(end - start) : 0;
-    const bool in_lds = staged && start >= b0 && end <= b1;
-    const int32_t lds0 = (int32_t)(start - b0);
-    auto col_at = [&](int32_t t) -> int32_t {
-        return in_lds ? s_cols[lds0 + t] : cols[start + t];
-    };
 
-    // The lane of word 0 validates every column and reports the verdict with
-    // its part; other lanes only clamp column indices so that no read leaves
-    // the index.
-    bool bad = false;
-    if (active && w == 0) {
-        bad = !ok_range;
-        for (int32_t t = 0; t < L; ++t) {
-            const int32_t col = col_at(t);
-            bad |= (col < 0 || col >= m);
-        }
+    // Stage the columns of candidates [c_lo, c_hi] in LDS when they fit and
+    // every lane's series lies inside the staged span (always, for a
+    // well-formed CBF); otherwise the whole workgroup reads them from global
+    // memory.  The choice is uniform over the workgroup.
+    const uint32_t i0 = tile * (uint32_t)kBlock;
+    const uint32_t c_lo = i0 / Wu;
+    const uint32_t c_hi = min((i0 + kBlock - 1) / Wu, (uint32_t)P - 1);
+    const int64_t b0 = offsets[R.cand_base + c_lo], b1 = offsets[R.cand_base + c_hi + 1];
+    const bool span_ok = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
+    const bool lane_ok = !ok_range || (start >= b0 && end <= b1);
+    const bool use_lds = __syncthreads_and(span_ok && lane_ok) != 0;
+    if (use_lds) {
+        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += kBlock) s_cols[e] = cols[b0 + e];
+        __syncthreads();
     }
+    const int32_t lds0 = (int32_t)(start - b0);
 
     const uint64_t valid = (active && ok_range) ? tail_bits(n, w, W) : 0ull;
     uint64_t cu[K + 1], cd[K + 1];
 #pragma unroll
     for (int i = 0; i <= K; ++i) cu[i] = cd[i] = 0ull;
+    bool bad = false;
 
-    if (valid) {
-        const uint64_t *base = idx + w;
-        int32_t p = col_at(0);
-        p = (p < 0 || p >= m) ? 0 : p;
-        for (int32_t t = 1; t < L; t += kUnroll) {
-            int32_t q[kUnroll];
-            uint64_t lu[kUnroll], ld[kUnroll];
+    // Per-lane work, instantiated for columns in LDS or in global memory.
+    auto lane_work = [&](auto from_lds) {
+        constexpr bool kLds = decltype(from_lds)::value;
+        auto col = [&](int32_t t) -> int32_t {
+            if constexpr (kLds) return s_cols[lds0 + t];
+            else return cols[start + t];
+        };
+        // The lane of word 0 validates every column (batched, branch-free
+        // reads) and reports the verdict with its part; other lanes only
+        // clamp column indices so that no read leaves the index.
+        if (active && w == 0) {
+            bad = !ok_range;
+            for (int32_t t = 0; t < L; t += U) {
+                int32_t v[U];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                q[u] = 0;
-                if (t + u < L) {
-                    const int32_t v = col_at(t + u);
-                    q[u] = (v < 0 || v >= m) ? 0 : v;
-                }
+                for (int u = 0; u < U; ++u) v[u] = col(min(t + u, L - 1));
+#pragma unroll
+                for (int u = 0; u < U; ++u) bad |= (v[u] < 0 || v[u] >= m);
             }
-            int32_t pp = p;
-            uint8_t tf[kUnroll];
+        }
+        if (!valid) return;
+        const auto base = idx + w;
+        const int32_t last = L - 1;
+        int32_t p = col(0);
+        p = (p < 0 || p >= m) ? 0 : p;
+        for (int32_t t = 1; t < L; t += U) {
+            // Column reads and order-word loads of the batch are issued
+            // unconditionally (indices past the end repeat the last column,
+            // a harmless in-bounds read whose word is then ignored).
+            int32_t q[U];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                lu[u] = ~0ull;
-                ld[u] = ~0ull;
-                tf[u] = 0;
-                if (t + u < L) {
-                    const int64_t pq = (int64_t)pp * m + q[u];
-                    lu[u] = base[pq * wpad];
-                    if (NEG) tf[u] = tie[pq];
-                    pp = q[u];
-                }
+            for (int u = 0; u < U; ++u) {
+                const int32_t v = col(min(t + u, last));
+                q[u] = (v < 0 || v >= m) ? 0 : v;
+            }
+            uint64_t lu[U], ld[U];
+            uint8_t tf[U];
+            int32_t pp = p;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t pq = (int64_t)pp * m + q[u];
+                lu[u] = base[pq * wpad];
+                if (NEG) tf[u] = tie[pq];
+                pp = q[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = t + u < L;
+                lu[u] = in ? lu[u] : ~0ull;
+                if (NEG) tf[u] = in ? tf[u] : 0;
             }
             if (NEG) {
                 // lt(q,p) is the complement of lt(p,q) unless the pair ties.
                 pp = p;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (t + u < L) {
-                        ld[u] = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
-                        pp = q[u];
-                    }
+                for (int u = 0; u < U; ++u) {
+                    ld[u] = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
+                    pp = q[u];
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) fold<K, NEG>(cu, cd, lu[u], ld[u]);
+            for (int u = 0; u < U; ++u) fold<K, NEG>(cu, cd, lu[u], NEG ? ld[u] : 0ull);
             p = pp;
             const uint64_t dead = NEG ? (cu[K] & cd[K]) : cu[K];
             if ((valid & ~dead) == 0ull) break;
         }
-    }
+    };
+    if (use_lds)
+        lane_work(std::true_type{});
+    else
+        lane_work(std::false_type{});
+
     const uint64_t pos = valid & ~cu[K];
     const uint64_t neg = NEG ? (valid & ~cd[K]) : 0ull;
     if (masks && active) {
-        masks[((int64_t)c * 2 + 0) * W + w] = pos;
-        masks[((int64_t)c * 2 + 1) * W + w] = neg;
+        masks[R.mask_base + ((int64_t)cl * 2 + 0) * W + w] = pos;
+        masks[R.mask_base + ((int64_t)cl * 2 + 1) * W + w] = neg;
     }
 
     // Segmented sum over lanes of the same candidate (lanes hold consecutive
@@ -414,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     // head gets the run's row count (low 16 bits, <= 64*64) and its number
     // of words (high bits), then reports them once.
     int32_t packed = active ? (__popcll(pos | neg) | (1 << 16)) : 0;
-    const int32_t cc = (int32_t)c;
+    const int32_t cc = (int32_t)cl;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
         const int32_t v = __shfl_down(packed, off);
@@ -427,6 +461,68 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     if (active && head)
         finish_part(c, (uint32_t)(packed & 0xFFFF), bad, packed >> 16, W, L, sigma, logt, acc,
                     counts, fitness);
+}
+
+template <int K, bool NEG, int U>
+__global__ __launch_bounds__(kBlock) void eval_index_kernel(
+    IndexRun R, const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols,
+    int64_t n_entries, int32_t sigma, uint64_t *__restrict__ masks,
+    unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
+    double *__restrict__ fitness) {
+    index_tile<K, NEG, U>(R, blockIdx.x, offsets, cols, n_entries, sigma, masks, acc, counts,
+                          fitness);
+}
+
+// --------------------------------------------------- batched (many runs) --
+//
+// One persistent launch evaluates one population per run for many runs with
+// matrices of different shapes.  The work is a queue of tiles (kBlock
+// consecutive (candidate, word) items of one run), run after run; each
+// workgroup takes the next tile with an atomic until the queue is empty.
+// The last workgroup to leave resets the queue, so the launch can be
+// replayed (a captured graph) without any clearing step.  work[0] is the
+// next tile, work[1] the number of workgroups that have left.
+template <int K, bool NEG, int U>
+__global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
+    const IndexRun *__restrict__ runs, const uint32_t *__restrict__ tile_base, int32_t n_runs,
+    unsigned int *__restrict__ work, const int32_t *__restrict__ offsets,
+    const int32_t *__restrict__ cols, int64_t n_entries, int32_t sigma,
+    uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
+    int32_t *__restrict__ counts, double *__restrict__ fitness) {
+    __shared__ uint32_t s_tile;
+    __shared__ int32_t s_run;
+    const uint32_t total_tiles = tile_base[n_runs];
+    for (;;) {
+        __syncthreads();  // the previous tile is finished by every wave
+        if (threadIdx.x == 0) {
+            const uint32_t t = atomicAdd(work, 1u);
+            int32_t r = 0;
+            if (t < total_tiles) {
+                // last run whose first tile is <= t
+                int32_t lo = 0, hi = n_runs - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                r = lo;
+            }
+            s_tile = t;
+            s_run = r;
+        }
+        __syncthreads();
+        const uint32_t t = s_tile;
+        if (t >= total_tiles) break;  // uniform
+        const int32_t r = s_run;
+        index_tile<K, NEG, U>(runs[r], t - tile_base[r], offsets, cols, n_entries, sigma, masks,
+                              acc, counts, fitness);
+    }
+    if (threadIdx.x == 0) {
+        const unsigned left = atomicAdd(work + 1, 1u);
+        if (left == gridDim.x - 1) {
+            atomicExch(work, 0u);
+            atomicExch(work + 1, 0u);
+        }
+    }
 }
 
 }  // namespace
@@ -481,31 +577,72 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
     return hipGetLastError();
 }
 
-template <int K>
-static void launch_index_k(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
-                           int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream) {
-    const int64_t total = (int64_t)e.P * W;
+template <int K, int U>
+static void launch_index_k(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
+    const int64_t total = (int64_t)R.P * R.W;
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
     if (e.negative)
-        hipLaunchKernelGGL((eval_index_kernel<K, true>), grid, dim3(kBlock), 0, stream, idx, n, m,
-                           W, wpad, tie, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
-                           e.masks, e.acc, e.counts, e.fitness);
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U>), grid, dim3(kBlock), 0, stream, R,
+                           e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
+                           e.fitness);
     else
-        hipLaunchKernelGGL((eval_index_kernel<K, false>), grid, dim3(kBlock), 0, stream, idx, n,
-                           m, W, wpad, tie, e.offsets, e.cols, e.P, e.n_entries, e.sigma, e.logt,
-                           e.masks, e.acc, e.counts, e.fitness);
+        hipLaunchKernelGGL((eval_index_kernel<K, false, U>), grid, dim3(kBlock), 0, stream, R,
+                           e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
+                           e.fitness);
 }
 
 hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
                              int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream) {
+    const IndexRun R{idx, tie, e.logt, n, W, wpad, m, e.P, 0, 0};
     switch (e.k) {
-    case 0: launch_index_k<0>(idx, tie, n, m, W, wpad, e, stream); break;
-    case 1: launch_index_k<1>(idx, tie, n, m, W, wpad, e, stream); break;
-    case 2: launch_index_k<2>(idx, tie, n, m, W, wpad, e, stream); break;
-    case 3: launch_index_k<3>(idx, tie, n, m, W, wpad, e, stream); break;
+    case 0: launch_index_k<0, kUnroll>(R, e, stream); break;
+    case 1: launch_index_k<1, kUnroll>(R, e, stream); break;
+    case 2: launch_index_k<2, kUnroll>(R, e, stream); break;
+    case 3: launch_index_k<3, kUnroll>(R, e, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int K, int U>
+static void launch_batch_k(const BatchLaunch &b, hipStream_t stream) {
+    if (b.negative)
+        hipLaunchKernelGGL((eval_index_batch_kernel<K, true, U>), dim3(b.grid), dim3(kBlock), 0,
+                           stream, b.runs, b.tile_base, b.n_runs, b.work, b.offsets, b.cols,
+                           b.n_entries, b.sigma, b.masks, b.acc, b.counts, b.fitness);
+    else
+        hipLaunchKernelGGL((eval_index_batch_kernel<K, false, U>), dim3(b.grid), dim3(kBlock), 0,
+                           stream, b.runs, b.tile_base, b.n_runs, b.work, b.offsets, b.cols,
+                           b.n_entries, b.sigma, b.masks, b.acc, b.counts, b.fitness);
+}
+
+template <int U>
+static hipError_t launch_batch_u(const BatchLaunch &b, hipStream_t stream) {
+    switch (b.k) {
+    case 0: launch_batch_k<0, U>(b, stream); break;
+    case 1: launch_batch_k<1, U>(b, stream); break;
+    case 2: launch_batch_k<2, U>(b, stream); break;
+    case 3: launch_batch_k<3, U>(b, stream); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int batch_wgs_per_cu() {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, eval_index_batch_kernel<1, true, 4>,
+                                                     kBlock, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream) {
+    switch (b.unroll) {
+    case 2: return launch_batch_u<2>(b, stream);
+    case 4: return launch_batch_u<4>(b, stream);
+    case 8: return launch_batch_u<8>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ebic

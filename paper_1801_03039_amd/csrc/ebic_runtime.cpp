@@ -265,6 +265,11 @@ bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
 
 namespace ebic {
 void set_thread_error(const char *msg) { g_tls_error = msg; }
+ebic_status ensure_index(ebic_ctx *ctx) { return build_index(ctx); }
+bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
+               ebic_status *st) {
+    return check_cbf(ctx, offsets, cols, P, st);
+}
 }  // namespace ebic
 
 extern "C" {

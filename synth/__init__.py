@@ -33,6 +33,7 @@ __all__ = [
     "unpack_cbf",
     "adversarial_matrix",
     "tiny_tie_matrix",
+    "batched_workload",
 ]
 
 
@@ -114,6 +115,27 @@ WORKLOADS = {
         sigma=50, max_violations=1, negative_trends=True,
         population=2048, len_min=3, len_max=20, generations=300),
 }
+
+
+def batched_workload(r: int, rows=(500, 50000), cols=(20, 1000), population: int = 1024,
+                     generations: int = 100) -> Workload:
+    """Run r of the batched setting: N log-uniform in ``rows``, M uniform in
+    ``cols``, N(0,1) background, 1-10 exact rising biclusters of
+    U{50..min(500, N/(2k))} rows x U{4..min(15, M/2)} columns, matrix seed r
+    (shapes drawn from an independent stream keyed by r)."""
+    import math
+    rng = np.random.default_rng([4, int(r)])
+    n = int(round(math.exp(rng.uniform(math.log(rows[0]), math.log(rows[1])))))
+    m = int(rng.integers(cols[0], cols[1] + 1))
+    k = int(rng.integers(1, 11))
+    r_hi = max(2, min(500, n // (2 * k)))
+    c_hi = max(2, min(15, m // 2))
+    return Workload(
+        name=f"batched-{r}", n_rows=n, n_cols=m, seed=int(r), background="normal",
+        n_planted=k, planted_rows=(min(50, r_hi), r_hi), planted_cols=(min(4, c_hi), c_hi),
+        noise_sd=0.01, noise_then_sort=True, overlap_max=0.0, descending_every_other=False,
+        sigma=25, max_violations=0, negative_trends=False,
+        population=population, len_min=3, len_max=min(20, m), generations=generations)
 
 
 def _background(rng: np.random.Generator, kind: str, n: int, m: int) -> np.ndarray:

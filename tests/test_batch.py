@@ -1,0 +1,165 @@
+"""GPU: batched evaluation and batched runs (many matrices, one launch per
+generation) against the CPU oracle, run by run, bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import evolve as oev
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[batch] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_03039_amd as e
+    return e
+
+
+SHAPES = [(1, 5), (65, 9), (200, 50), (1000, 30), (130, 3), (4096, 12)]
+
+
+@pytest.fixture(scope="module")
+def mats():
+    rng = np.random.default_rng(21)
+    out = []
+    for i, (n, m) in enumerate(SHAPES):
+        a = synth.adversarial_matrix(rng, n, m) if i % 2 else rng.standard_normal((n, m)).astype(np.float32)
+        out.append(a)
+    return out
+
+
+def _pops(rng, mats, skip=()):
+    pops = []
+    for i, a in enumerate(mats):
+        if i in skip:
+            pops.append(None)
+            continue
+        m = a.shape[1]
+        pop = synth.random_population(rng, m, int(rng.integers(1, 300)), 1, min(m, 12))
+        pops.append(synth.pack_cbf(pop))
+    return pops
+
+
+def _check_runs(mats, pops, got, sigma, k, neg, masks=True):
+    for a, pop, g in zip(mats, pops, got):
+        if pop is None:
+            assert g is None
+            continue
+        ref = oracle.evaluate(a, pop[0], pop[1], sigma=sigma, max_violations=k,
+                              negative_trends=neg, want_masks=masks)
+        assert np.array_equal(g["counts"], ref["counts"])
+        assert np.array_equal(g["fitness"].view(np.int64), ref["fitness"].view(np.int64))
+        if masks:
+            assert np.array_equal(g["masks"], ref["masks"])
+
+
+def test_batch_evaluate_matches_oracle(E, mats):
+    rng = np.random.default_rng(1)
+    with E.Batch(mats) as b:
+        for k in (0, 1, 3):
+            for neg in (False, True):
+                pops = _pops(rng, mats, skip=(2,) if k == 1 else ())
+                _note(f"evaluate k={k} neg={neg}")
+                got = b.evaluate(pops, sigma=6, max_violations=k, negative_trends=neg,
+                                 want_masks=True)
+                _check_runs(mats, pops, got, 6, k, neg)
+
+
+def test_graph_replays_interleaved_with_eager_work(E, mats):
+    # The captured graph is replayed with a new run table each time, with
+    # eager single-context work and host synchronisation in between; every
+    # replay must equal the oracle.
+    import torch
+    rng = np.random.default_rng(2)
+    with E.Batch(mats) as b, E.Context(mats[3]) as ctx:
+        for rep in range(5):
+            pops = _pops(rng, mats)
+            _note(f"replay {rep}")
+            got = b.evaluate(pops, sigma=4, max_violations=1, negative_trends=True)
+            _check_runs(mats, pops, got, 4, 1, True, masks=False)
+            eager = ctx.evaluate(*pops[3], sigma=4, max_violations=1, negative_trends=True)
+            assert np.array_equal(eager["counts"], got[3]["counts"])
+            x = torch.arange(1000, device="cuda").sum()
+            torch.cuda.synchronize()
+            assert int(x) == 499500
+
+
+def test_every_launch_shape_agrees(E, mats):
+    rng = np.random.default_rng(3)
+    pops = _pops(rng, mats)
+    with E.Batch(mats) as b:
+        ref = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True, want_masks=True,
+                         tune=True)
+        t = b.tuning()
+        assert t["unroll"] in (2, 4, 8) and t["workgroups"] >= 1 and t["best_ms"] > 0
+        _check_runs(mats, pops, ref, 5, 2, True)
+        for wg in (1, 0, 7, 5000):
+            for u in (2, 4, 8):
+                _note(f"shape wg={wg} unroll={u}")
+                b.set_tuning(wg, u)
+                got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
+                                 want_masks=True)
+                for g, r in zip(got, ref):
+                    assert np.array_equal(g["counts"], r["counts"])
+                    assert np.array_equal(g["masks"], r["masks"])
+
+
+def test_batch_errors(E, mats):
+    with E.Batch(mats[:2]) as b:
+        bad = [(np.array([0, 2]), np.array([0, 99])), None]
+        with pytest.raises(E.EbicError):
+            b.evaluate(bad, sigma=1)
+        with pytest.raises(E.EbicError):
+            b.evaluate([None, None], sigma=1, max_violations=4)
+        assert b.evaluate([None, None], sigma=1) == [None, None]
+
+
+def test_batch_evolve_matches_oracle_runs(E):
+    rng = np.random.default_rng(4)
+    shapes = [(150, 20), (300, 12), (90, 30), (500, 8)]
+    mats_ = [rng.standard_normal(s).astype(np.float32) for s in shapes]
+    seeds = [11, 12, 13, 14]
+    G = 6
+    cfg = E.EvolveConfig(population=60, len_min=3, len_max=7, eval=E.Trend(8),
+                         expand=E.Trend(8, 1, True))
+    gens = {r: [] for r in range(len(mats_))}
+    with E.Batch(mats_) as b:
+        _note("batch evolve")
+        res = b.evolve(seeds, G, cfg, on_generation=lambda r, g: gens[r].append(g), host_threads=3)
+    for r, (a, s) in enumerate(zip(mats_, seeds)):
+        op = oev.EvolveParams(population=60, len_min=3, len_max=7, eval=oev.TrendParams(8),
+                              expand=oev.TrendParams(8, 1, True))
+        ref = oev.evolve(a, s, G, op)
+        assert len(gens[r]) == len(ref.history)
+        for g, h in zip(gens[r], ref.history):
+            assert g.population == h.population
+            assert np.array_equal(g.counts, h.counts)
+            assert np.array_equal(g.fitness.view(np.int64), h.fitness.view(np.int64))
+        assert [x["cols"] for x in res[r].biclusters] == [x["cols"] for x in ref.biclusters]
+        for x, y in zip(res[r].biclusters, ref.biclusters):
+            assert x["count"] == y["count"] and x["fitness"] == y["fitness"]
+            assert np.array_equal(x["mask_words"], y["mask_words"])
+
+
+def test_batched_workload_shapes_one_generation(E):
+    # Four runs of the batched setting at full size (up to 50000 rows and
+    # 1000 columns), one population each, against the oracle.
+    ws = [synth.batched_workload(r) for r in range(4)]
+    data = [synth.make_matrix(w) for w in ws]
+    rng = np.random.default_rng(5)
+    pops = [synth.pack_cbf(synth.mixed_population(rng, w, pl, 256)) for w, (a, pl) in zip(ws, data)]
+    with E.Batch([a for a, _ in data]) as b:
+        _note("batched workload shapes")
+        got = b.evaluate(pops, sigma=25, tune=True)
+    _check_runs([a for a, _ in data], pops, got, 25, 0, False, masks=False)
