@@ -333,6 +333,49 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
                               ebic_batch_generation_fn on_generation, void *user,
                               int32_t host_threads, ebic_result **results);
 
+/*
+ * Surrogate fitness model for screening offspring: a 3-layer MLP over
+ * learned per-column embeddings (not in the paper; it only ranks
+ * candidates, every admitted candidate is still scored exactly).
+ *
+ *   x    = mean of the series' column embeddings E[c] (embed_dim each)
+ *   h1   = relu(W1 bf16(x) + b1)        W1: hidden x embed_dim
+ *   h2   = relu(W2 bf16(h1) + b2)       W2: hidden x hidden
+ *   y    = w3 . bf16(h2) + b3           w3: hidden
+ * Products use BF16 copies of the FP32 master weights on MFMA units with
+ * FP32 accumulation; training minimises (1/B) sum (y - target)^2 with Adam
+ * on the masters (gradients pass through the BF16 casts unchanged).
+ * Parameters, flattened FP32 in this order: E [n_cols][embed_dim],
+ * W1 [hidden][embed_dim], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
+ * w3 [hidden], b3 [1].  All reductions run in a fixed order, so results are
+ * deterministic on a given device.  Errors: message via ebic_last_error(NULL).
+ */
+typedef struct ebic_mlp ebic_mlp;
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ebic_mlp_config) */
+    int32_t embed_dim;          /* 32 */
+    int32_t hidden;             /* 256 */
+    float lr, beta1, beta2, eps;/* Adam: 1e-3, 0.9, 0.999, 1e-8 */
+} ebic_mlp_config;
+
+void ebic_mlp_defaults(ebic_mlp_config *c);
+/* Parameters initialised from SplitMix64(seed): E ~ U(-1,1), W1 ~
+ * U(+-sqrt(6/embed_dim)), W2 ~ U(+-sqrt(6/hidden)), w3 ~ U(+-sqrt(3/hidden)),
+ * biases 0. */
+ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t seed,
+                            int32_t device, ebic_mlp **out);
+ebic_status ebic_mlp_destroy(ebic_mlp *m);
+int64_t ebic_mlp_param_count(const ebic_mlp *m);
+ebic_status ebic_mlp_get_params(const ebic_mlp *m, float *params);
+ebic_status ebic_mlp_set_params(ebic_mlp *m, const float *params);   /* also resets Adam */
+/* Host CBF in, host outputs, blocking.  Columns must lie in [0, n_cols). */
+ebic_status ebic_mlp_predict(ebic_mlp *m, const int32_t *offsets, const int32_t *cols, int32_t B,
+                             float *y);
+ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
+                               int32_t B, const float *target, float *grad, float *loss);
+ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
+                                int32_t B, const float *target, float *loss);
+
 /* Message of the last error on ctx.  With ctx == NULL: the calling thread's
  * last error from a call that had no context (ebic_create*, argument errors
  * of ebic_evolve*, ebic_result_*); an evaluation failure inside

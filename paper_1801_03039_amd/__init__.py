@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     EvolveConfig,
     EvolveResult,
     Generation,
+    Mlp,
     Trend,
     evolve,
     evolve_with,

@@ -570,3 +570,96 @@ class Batch:
         _check(_batch_evolve(self._h, sd.ctypes.data, int(generations), ctypes.byref(p), gcb, None,
                              int(host_threads), res))
         return [_finish(_vp(res[r]), self.n_rows[r]) for r in range(R)]
+
+
+# ------------------------------------------------------------- surrogate MLP --
+
+class MlpConfig(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("embed_dim", _i32), ("hidden", _i32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+_mlp_defaults = _sig("ebic_mlp_defaults", None, [_P(MlpConfig)])
+_mlp_create = _sig("ebic_mlp_create", _i32, [_i32, _P(MlpConfig), _u64, _i32, _P(_vp)])
+_mlp_destroy = _sig("ebic_mlp_destroy", _i32, [_vp])
+_mlp_param_count = _sig("ebic_mlp_param_count", _i64, [_vp])
+_mlp_get_params = _sig("ebic_mlp_get_params", _i32, [_vp, _vp])
+_mlp_set_params = _sig("ebic_mlp_set_params", _i32, [_vp, _vp])
+_mlp_predict = _sig("ebic_mlp_predict", _i32, [_vp, _vp, _vp, _i32, _vp])
+_mlp_gradients = _sig("ebic_mlp_gradients", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _P(ctypes.c_float)])
+_mlp_train_step = _sig("ebic_mlp_train_step", _i32, [_vp, _vp, _vp, _i32, _vp, _P(ctypes.c_float)])
+EXPORTED += ["ebic_mlp_defaults", "ebic_mlp_create", "ebic_mlp_destroy", "ebic_mlp_param_count",
+             "ebic_mlp_get_params", "ebic_mlp_set_params", "ebic_mlp_predict",
+             "ebic_mlp_gradients", "ebic_mlp_train_step"]
+
+
+class Mlp:
+    """Surrogate fitness model on one GPU (``ebic_mlp_*``)."""
+
+    def __init__(self, n_cols: int, seed: int = 0, embed_dim: int = 32, hidden: int = 256,
+                 lr: float = 1e-3, device: int = 0):
+        cfg = MlpConfig()
+        _mlp_defaults(ctypes.byref(cfg))
+        cfg.embed_dim, cfg.hidden, cfg.lr = int(embed_dim), int(hidden), float(lr)
+        h = _vp()
+        _check(_mlp_create(int(n_cols), ctypes.byref(cfg), int(seed) & ((1 << 64) - 1),
+                           int(device), ctypes.byref(h)))
+        self._h = h
+        self.n_cols, self.embed_dim, self.hidden = int(n_cols), int(embed_dim), int(hidden)
+        self.n_params = int(_mlp_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _mlp_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        arr = np.ascontiguousarray(p, dtype=np.float32)
+        assert arr.size == self.n_params
+        _check(_mlp_set_params(self._h, arr.ctypes.data))
+
+    @staticmethod
+    def _cbf(offsets, cols):
+        o = np.ascontiguousarray(offsets, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        return o, c, len(o) - 1
+
+    def predict(self, offsets, cols) -> np.ndarray:
+        o, c, B = self._cbf(offsets, cols)
+        y = np.zeros(B, dtype=np.float32)
+        _check(_mlp_predict(self._h, o.ctypes.data, c.ctypes.data, B, y.ctypes.data))
+        return y
+
+    def gradients(self, offsets, cols, target):
+        o, c, B = self._cbf(offsets, cols)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_mlp_gradients(self._h, o.ctypes.data, c.ctypes.data, B, t.ctypes.data,
+                              g.ctypes.data, ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def train_step(self, offsets, cols, target) -> float:
+        o, c, B = self._cbf(offsets, cols)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_mlp_train_step(self._h, o.ctypes.data, c.ctypes.data, B, t.ctypes.data,
+                               ctypes.byref(loss)))
+        return float(loss.value)

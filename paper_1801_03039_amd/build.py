@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libebic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["ebic_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp"]
+SOURCES = ["ebic_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
+           "ebic_mlp_kernels.hip", "ebic_mlp.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
           "-I", INCLUDE, "-I", CSRC]
@@ -43,7 +44,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(BUILD_DIR, src + ".o")
         cmd = [cc, "-c"] + (HIP_ONLY if src.endswith(".hip") else []) + [path, "-o", obj] + COMMON
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -1,0 +1,371 @@
+// Surrogate MLP runtime: parameters, buffers and the forward / backward /
+// Adam sequences of the kernels in ebic_mlp_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ebic.h"
+#include "ebic_mlp.h"
+
+namespace ebic {
+void set_thread_error(const char *msg);
+}
+
+using namespace ebic;
+
+struct ebic_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int32_t M = 0, D = 0, H = 0;
+    ebic_mlp_config cfg{};
+    int64_t n_params = 0;
+    int64_t oE = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, ow3 = 0, ob3 = 0;
+    float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+    uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;
+    int64_t step = 0;
+    // per-batch buffers (capacity cap_B candidates, cap_L column entries)
+    int64_t cap_B = 0, cap_L = 0;
+    int32_t *off = nullptr, *cols = nullptr, *occ_start = nullptr, *occ_b = nullptr;
+    float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *y = nullptr, *t = nullptr, *dy = nullptr,
+          *sq = nullptr, *dZ2 = nullptr, *G1 = nullptr, *dZ1 = nullptr, *dX = nullptr;
+    uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
+    float *ws = nullptr;
+    int64_t cap_ws = 0;
+};
+
+namespace {
+
+constexpr int32_t kMaxSplits = 64;
+
+ebic_status mfail(ebic_status st, const std::string &msg) {
+    set_thread_error(msg.c_str());
+    return st;
+}
+
+#define MHIP(expr)                                                                           \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return mfail(_e == hipErrorOutOfMemory ? EBIC_E_NOMEM : EBIC_E_DEVICE,           \
+                         std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T *&p, int64_t n) {
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    return hipMalloc((void **)&p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+
+ebic_status reserve(ebic_mlp *m, int64_t B, int64_t L) {
+    const int64_t H = m->H, D = m->D;
+    if (B > m->cap_B) {
+        MHIP(hipStreamSynchronize(m->stream));
+        const int64_t c = std::max<int64_t>(B, m->cap_B * 2);
+        MHIP(dalloc(m->off, c + 1));
+        MHIP(dalloc(m->X, c * D));
+        MHIP(dalloc(m->Xb, c * D));
+        MHIP(dalloc(m->Z1, c * H));
+        MHIP(dalloc(m->H1b, c * H));
+        MHIP(dalloc(m->Z2, c * H));
+        MHIP(dalloc(m->H2b, c * H));
+        MHIP(dalloc(m->y, c));
+        MHIP(dalloc(m->t, c));
+        MHIP(dalloc(m->dy, c));
+        MHIP(dalloc(m->sq, c));
+        MHIP(dalloc(m->dZ2, c * H));
+        MHIP(dalloc(m->dZ2b, c * H));
+        MHIP(dalloc(m->G1, c * H));
+        MHIP(dalloc(m->dZ1, c * H));
+        MHIP(dalloc(m->dZ1b, c * H));
+        MHIP(dalloc(m->dX, c * D));
+        m->cap_B = c;
+    }
+    if (L > m->cap_L) {
+        MHIP(hipStreamSynchronize(m->stream));
+        const int64_t c = std::max<int64_t>(L, m->cap_L * 2);
+        MHIP(dalloc(m->cols, c));
+        MHIP(dalloc(m->occ_b, c));
+        m->cap_L = c;
+    }
+    const int64_t need_ws = (int64_t)kMaxSplits * std::max<int64_t>(H * H, H * D);
+    if (need_ws > m->cap_ws) {
+        MHIP(dalloc(m->ws, need_ws));
+        m->cap_ws = need_ws;
+    }
+    return EBIC_OK;
+}
+
+int32_t splits_for(int32_t B) { return std::max(1, std::min(kMaxSplits, B / 256)); }
+
+bool check_cbf(const ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t B) {
+    if (off[0] != 0) return false;
+    for (int32_t b = 0; b < B; ++b) {
+        if (off[b + 1] <= off[b]) return false;
+        for (int32_t i = off[b]; i < off[b + 1]; ++i)
+            if (cols[i] < 0 || cols[i] >= m->M) return false;
+    }
+    return true;
+}
+
+// Uploads a batch (CBF, occurrence lists by column, optional targets).
+ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t B,
+                   const float *target, bool occurrences) {
+    if (!off || !cols || B < 1) return mfail(EBIC_E_ARG, "need a non-empty CBF batch");
+    if (!check_cbf(m, off, cols, B)) return mfail(EBIC_E_RANGE, "malformed CBF or column out of range");
+    const int64_t L = off[B];
+    ebic_status st = reserve(m, B, L);
+    if (st != EBIC_OK) return st;
+    MHIP(hipMemcpyAsync(m->off, off, sizeof(int32_t) * ((size_t)B + 1), hipMemcpyHostToDevice,
+                        m->stream));
+    MHIP(hipMemcpyAsync(m->cols, cols, sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice,
+                        m->stream));
+    if (target)
+        MHIP(hipMemcpyAsync(m->t, target, sizeof(float) * (size_t)B, hipMemcpyHostToDevice,
+                            m->stream));
+    if (occurrences) {
+        // CSR by column: every occurrence of column j, candidates in order.
+        std::vector<int32_t> start((size_t)m->M + 1, 0), occ((size_t)L);
+        for (int64_t i = 0; i < L; ++i) ++start[(size_t)cols[i] + 1];
+        for (int32_t j = 0; j < m->M; ++j) start[(size_t)j + 1] += start[(size_t)j];
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int32_t b = 0; b < B; ++b)
+            for (int32_t i = off[b]; i < off[b + 1]; ++i) occ[(size_t)fill[(size_t)cols[i]]++] = b;
+        if (!m->occ_start) MHIP(hipMalloc((void **)&m->occ_start, sizeof(int32_t) * ((size_t)m->M + 1)));
+        MHIP(hipStreamSynchronize(m->stream));  // no kernel still reads the previous lists
+        MHIP(hipMemcpy(m->occ_start, start.data(), sizeof(int32_t) * start.size(),
+                       hipMemcpyHostToDevice));
+        MHIP(hipMemcpy(m->occ_b, occ.data(), sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice));
+    }
+    return EBIC_OK;
+}
+
+ebic_status forward(ebic_mlp *m, int32_t B) {
+    const int32_t D = m->D, H = m->H;
+    hipStream_t s = m->stream;
+    MHIP(mlp::pool_fwd(m->p + m->oE, D, m->off, m->cols, B, m->X, m->Xb, s));
+    mlp::Gemm l1{m->Xb, D, 1, m->W1b, 1, D, B, H, D, 1, m->p + m->ob1, 1, m->Z1, m->H1b, nullptr};
+    MHIP(mlp::gemm(l1, s));
+    mlp::Gemm l2{m->H1b, H, 1, m->W2b, 1, H, B, H, H, 1, m->p + m->ob2, 1, m->Z2, m->H2b, nullptr};
+    MHIP(mlp::gemm(l2, s));
+    MHIP(mlp::out_fwd(m->H2b, m->w3b, m->p + m->ob3, B, H, m->y, s));
+    return EBIC_OK;
+}
+
+// Gradients of the mean squared error into m->g (layout of the parameters).
+ebic_status backward(ebic_mlp *m, int32_t B) {
+    const int32_t D = m->D, H = m->H, S = splits_for(B);
+    hipStream_t s = m->stream;
+    float *g = m->g;
+    MHIP(mlp::loss(m->y, m->t, B, m->dy, m->sq, s));
+    MHIP(mlp::dw3(m->H2b, m->dy, B, H, S, m->ws, g + m->ow3, s));
+    MHIP(mlp::colsum(m->dy, nullptr, B, 1, S, m->ws, g + m->ob3, s));
+    MHIP(mlp::out_bwd(m->dy, m->w3b, m->Z2, B, H, m->dZ2, m->dZ2b, s));
+    MHIP(mlp::colsum(m->dZ2, nullptr, B, H, S, m->ws, g + m->ob2, s));
+    // dW2[n][k] = sum_b dZ2[b][n] h1[b][k]
+    mlp::Gemm gw2{m->dZ2b, 1, H, m->H1b, H, 1, H, H, B, S, nullptr, 0, g + m->oW2, nullptr, m->ws};
+    MHIP(mlp::gemm(gw2, s));
+    // G1[b][k] = sum_n dZ2[b][n] W2[n][k]
+    mlp::Gemm gh1{m->dZ2b, H, 1, m->W2b, H, 1, B, H, H, 1, nullptr, 0, m->G1, nullptr, nullptr};
+    MHIP(mlp::gemm(gh1, s));
+    MHIP(mlp::relu_bwd(m->G1, m->Z1, (int64_t)B * H, m->dZ1, m->dZ1b, s));
+    MHIP(mlp::colsum(m->dZ1, nullptr, B, H, S, m->ws, g + m->ob1, s));
+    // dW1[h][d] = sum_b dZ1[b][h] x[b][d]
+    mlp::Gemm gw1{m->dZ1b, 1, H, m->Xb, D, 1, H, D, B, S, nullptr, 0, g + m->oW1, nullptr, m->ws};
+    MHIP(mlp::gemm(gw1, s));
+    // dX[b][d] = sum_h dZ1[b][h] W1[h][d]
+    mlp::Gemm gx{m->dZ1b, H, 1, m->W1b, D, 1, B, D, H, 1, nullptr, 0, m->dX, nullptr, nullptr};
+    MHIP(mlp::gemm(gx, s));
+    MHIP(mlp::pool_bwd(m->dX, D, m->off, m->occ_start, m->occ_b, m->M, g + m->oE, s));
+    return EBIC_OK;
+}
+
+ebic_status refresh_bf16(ebic_mlp *m) {
+    MHIP(mlp::cast_bf16(m->p + m->oW1, (int64_t)m->H * m->D, m->W1b, m->stream));
+    MHIP(mlp::cast_bf16(m->p + m->oW2, (int64_t)m->H * m->H, m->W2b, m->stream));
+    MHIP(mlp::cast_bf16(m->p + m->ow3, (int64_t)m->H, m->w3b, m->stream));
+    return EBIC_OK;
+}
+
+float host_loss(ebic_mlp *m, int32_t B, ebic_status *st) {
+    std::vector<float> sq((size_t)B);
+    hipError_t e = hipMemcpyAsync(sq.data(), m->sq, sizeof(float) * (size_t)B,
+                                  hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        *st = mfail(EBIC_E_DEVICE, std::string("loss copy: ") + hipGetErrorString(e));
+        return 0.f;
+    }
+    double acc = 0.0;
+    for (float v : sq) acc += v;
+    *st = EBIC_OK;
+    return (float)(acc / B);
+}
+
+struct SplitMix {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    float sym(float a) { return ((float)(next() >> 40) * (1.0f / 16777216.0f) * 2.f - 1.f) * a; }
+};
+
+}  // namespace
+
+extern "C" {
+
+void ebic_mlp_defaults(ebic_mlp_config *c) {
+    if (!c) return;
+    *c = ebic_mlp_config{sizeof(ebic_mlp_config), 32, 256, 1e-3f, 0.9f, 0.999f, 1e-8f};
+}
+
+ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t seed,
+                            int32_t device, ebic_mlp **out) {
+    if (!out || n_cols < 1 || !cfg || cfg->struct_size < sizeof(ebic_mlp_config))
+        return mfail(EBIC_E_ARG, "need n_cols >= 1, a config and out");
+    if (cfg->embed_dim < 1 || cfg->hidden < 1 || cfg->embed_dim > 4096 || cfg->hidden > 4096)
+        return mfail(EBIC_E_ARG, "embed_dim and hidden must be in [1, 4096]");
+    *out = nullptr;
+    std::unique_ptr<ebic_mlp> m(new (std::nothrow) ebic_mlp());
+    if (!m) return mfail(EBIC_E_NOMEM, "cannot allocate model");
+    m->device = device;
+    m->M = n_cols;
+    m->D = cfg->embed_dim;
+    m->H = cfg->hidden;
+    m->cfg = *cfg;
+    const int64_t M = n_cols, D = m->D, H = m->H;
+    m->oE = 0;
+    m->oW1 = m->oE + M * D;
+    m->ob1 = m->oW1 + H * D;
+    m->oW2 = m->ob1 + H;
+    m->ob2 = m->oW2 + H * H;
+    m->ow3 = m->ob2 + H;
+    m->ob3 = m->ow3 + H;
+    m->n_params = m->ob3 + 1;
+    std::vector<float> init((size_t)m->n_params, 0.f);
+    SplitMix rng{seed};
+    for (int64_t i = 0; i < M * D; ++i) init[(size_t)(m->oE + i)] = rng.sym(1.f);
+    for (int64_t i = 0; i < H * D; ++i) init[(size_t)(m->oW1 + i)] = rng.sym(std::sqrt(6.f / D));
+    for (int64_t i = 0; i < H * H; ++i) init[(size_t)(m->oW2 + i)] = rng.sym(std::sqrt(6.f / H));
+    for (int64_t i = 0; i < H; ++i) init[(size_t)(m->ow3 + i)] = rng.sym(std::sqrt(3.f / H));
+    auto fail = [&](hipError_t e, const char *w) {
+        ebic_mlp_destroy(m.release());
+        return mfail(e == hipErrorOutOfMemory ? EBIC_E_NOMEM : EBIC_E_DEVICE,
+                     std::string(w) + ": " + hipGetErrorString(e));
+    };
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = dalloc(m->p, m->n_params);
+    if (e == hipSuccess) e = dalloc(m->g, m->n_params);
+    if (e == hipSuccess) e = dalloc(m->m1, m->n_params);
+    if (e == hipSuccess) e = dalloc(m->m2, m->n_params);
+    if (e == hipSuccess) e = dalloc(m->W1b, H * D);
+    if (e == hipSuccess) e = dalloc(m->W2b, H * H);
+    if (e == hipSuccess) e = dalloc(m->w3b, H);
+    if (e != hipSuccess) return fail(e, "model buffers");
+    ebic_status st = ebic_mlp_set_params(m.get(), init.data());
+    if (st != EBIC_OK) {
+        ebic_mlp_destroy(m.release());
+        return st;
+    }
+    *out = m.release();
+    return EBIC_OK;
+}
+
+ebic_status ebic_mlp_destroy(ebic_mlp *m) {
+    if (!m) return EBIC_OK;
+    (void)hipSetDevice(m->device);
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    void *bufs[] = {m->p, m->g, m->m1, m->m2, m->W1b, m->W2b, m->w3b, m->off, m->cols,
+                    m->occ_start, m->occ_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
+                    m->dZ2, m->G1, m->dZ1, m->dX, m->Xb, m->H1b, m->H2b, m->dZ2b, m->dZ1b, m->ws};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (m->stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+    return EBIC_OK;
+}
+
+int64_t ebic_mlp_param_count(const ebic_mlp *m) { return m ? m->n_params : 0; }
+
+ebic_status ebic_mlp_get_params(const ebic_mlp *m, float *params) {
+    if (!m || !params) return mfail(EBIC_E_ARG, "null argument");
+    MHIP(hipSetDevice(m->device));
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(params, m->p, sizeof(float) * (size_t)m->n_params, hipMemcpyDeviceToHost));
+    return EBIC_OK;
+}
+
+ebic_status ebic_mlp_set_params(ebic_mlp *m, const float *params) {
+    if (!m || !params) return mfail(EBIC_E_ARG, "null argument");
+    MHIP(hipSetDevice(m->device));
+    MHIP(hipStreamSynchronize(m->stream));
+    MHIP(hipMemcpy(m->p, params, sizeof(float) * (size_t)m->n_params, hipMemcpyHostToDevice));
+    MHIP(hipMemset(m->m1, 0, sizeof(float) * (size_t)m->n_params));
+    MHIP(hipMemset(m->m2, 0, sizeof(float) * (size_t)m->n_params));
+    m->step = 0;
+    ebic_status st = refresh_bf16(m);
+    if (st != EBIC_OK) return st;
+    MHIP(hipStreamSynchronize(m->stream));
+    return EBIC_OK;
+}
+
+ebic_status ebic_mlp_predict(ebic_mlp *m, const int32_t *offsets, const int32_t *cols, int32_t B,
+                             float *y) {
+    if (!m || !y) return mfail(EBIC_E_ARG, "null argument");
+    MHIP(hipSetDevice(m->device));
+    ebic_status st = upload(m, offsets, cols, B, nullptr, false);
+    if (st != EBIC_OK) return st;
+    if ((st = forward(m, B)) != EBIC_OK) return st;
+    MHIP(hipMemcpyAsync(y, m->y, sizeof(float) * (size_t)B, hipMemcpyDeviceToHost, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    return EBIC_OK;
+}
+
+ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
+                               int32_t B, const float *target, float *grad, float *loss) {
+    if (!m || !target || !grad) return mfail(EBIC_E_ARG, "null argument");
+    MHIP(hipSetDevice(m->device));
+    ebic_status st = upload(m, offsets, cols, B, target, true);
+    if (st != EBIC_OK) return st;
+    if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
+    MHIP(hipMemcpyAsync(grad, m->g, sizeof(float) * (size_t)m->n_params, hipMemcpyDeviceToHost,
+                        m->stream));
+    const float l = host_loss(m, B, &st);
+    if (st != EBIC_OK) return st;
+    if (loss) *loss = l;
+    return EBIC_OK;
+}
+
+ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
+                                int32_t B, const float *target, float *loss) {
+    if (!m || !target) return mfail(EBIC_E_ARG, "null argument");
+    MHIP(hipSetDevice(m->device));
+    ebic_status st = upload(m, offsets, cols, B, target, true);
+    if (st != EBIC_OK) return st;
+    if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
+    m->step += 1;
+    const float c1 = 1.f - std::pow(m->cfg.beta1, (float)m->step);
+    const float c2 = 1.f - std::pow(m->cfg.beta2, (float)m->step);
+    MHIP(mlp::adam(m->p, m->g, m->m1, m->m2, m->n_params, m->cfg.lr, m->cfg.beta1, m->cfg.beta2,
+                   m->cfg.eps, c1, c2, m->stream));
+    if ((st = refresh_bf16(m)) != EBIC_OK) return st;
+    const float l = host_loss(m, B, &st);  // loss of the pre-step parameters
+    if (st != EBIC_OK) return st;
+    if (loss) *loss = l;
+    return EBIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Internal launchers of the surrogate MLP kernels (ebic_mlp_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ebic {
+namespace mlp {
+
+// C[M x N] = sum_k A(m,k) B(k,n), BF16 operands by strides, FP32 result.
+// splits > 1: K is cut into `splits` ranges whose partial products go to ws
+// (splits*M*N floats) and are then summed in order into out_f32.
+struct Gemm {
+    const uint16_t *A;
+    int64_t am, ak;
+    const uint16_t *B;
+    int64_t bk, bn;
+    int32_t M, N, K;
+    int32_t splits;
+    const float *bias;     // per n, or nullptr (splits == 1 only)
+    int32_t relu;          // out_bf16 holds relu(v) when set
+    float *out_f32;        // or nullptr (splits == 1)
+    uint16_t *out_bf16;    // or nullptr (splits == 1 only)
+    float *ws;             // splits > 1
+};
+
+hipError_t pool_fwd(const float *E, int32_t D, const int32_t *off, const int32_t *cols, int32_t B,
+                    float *X, uint16_t *Xb, hipStream_t s);
+hipError_t pool_bwd(const float *dX, int32_t D, const int32_t *off, const int32_t *occ_start,
+                    const int32_t *occ_b, int32_t M, float *dE, hipStream_t s);
+hipError_t gemm(const Gemm &g, hipStream_t s);
+hipError_t colsum(const float *X, const float *w, int32_t B, int32_t N, int32_t splits, float *ws,
+                  float *out, hipStream_t s);
+hipError_t dw3(const uint16_t *H2b, const float *dy, int32_t B, int32_t N, int32_t splits,
+               float *ws, float *out, hipStream_t s);
+hipError_t out_fwd(const uint16_t *H2b, const uint16_t *w3b, const float *b3, int32_t B, int32_t H,
+                   float *y, hipStream_t s);
+hipError_t loss(const float *y, const float *t, int32_t B, float *dy, float *sq, hipStream_t s);
+hipError_t out_bwd(const float *dy, const uint16_t *w3b, const float *Z2, int32_t B, int32_t H,
+                   float *dZ2, uint16_t *dZ2b, hipStream_t s);
+hipError_t relu_bwd(const float *G, const float *Z, int64_t n, float *dZ, uint16_t *dZb,
+                    hipStream_t s);
+hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, float lr, float beta1,
+                float beta2, float eps, float c1, float c2, hipStream_t s);
+hipError_t cast_bf16(const float *src, int64_t n, uint16_t *dst, hipStream_t s);
+
+}  // namespace mlp
+}  // namespace ebic
