@@ -376,6 +376,42 @@ ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_
 ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
                                 int32_t B, const float *target, float *loss);
 
+/*
+ * Surrogate-screened run (not in the paper).  As ebic_evolve, except that
+ * after `warmup_generations` a generation draws oversample x (P - elites)
+ * novel children and keeps the P - elites that the surrogate MLP ranks
+ * highest (see ebic_evolve's Step 3 readings for how children are drawn).
+ * Every kept child is scored exactly on the GPU; only kept children enter
+ * the tabu list.  The model is trained each generation (train_steps Adam
+ * steps) on the exact (candidate, log(1 + fitness)) pairs of the last
+ * replay_generations generations.  Before each generation is scored, the
+ * model's predictions for its new members are compared with their exact
+ * fitness (Spearman rank correlation); a generation is screened only if the
+ * previous generation's correlation reached min_rank_corr, otherwise it is
+ * bred exactly as in ebic_evolve (the plain method is the fallback).
+ * on_surrogate (may be NULL) reports, per generation: whether it was
+ * screened, the rank correlation, the training loss and the pool size.
+ */
+typedef void (*ebic_surrogate_fn)(void *user, int32_t gen, int32_t screened, double rank_corr,
+                                  double train_loss, int32_t pool);
+typedef struct {
+    uint32_t struct_size;         /* sizeof(ebic_surrogate_params) */
+    int32_t oversample;           /* 8 */
+    int32_t warmup_generations;   /* 3 */
+    int32_t train_steps;          /* 4 */
+    int32_t replay_generations;   /* 4 */
+    double min_rank_corr;         /* 0.1 */
+    uint64_t mlp_seed;
+    ebic_mlp_config mlp;
+    ebic_surrogate_fn on_surrogate;
+    void *user;
+} ebic_surrogate_params;
+
+void ebic_surrogate_defaults(ebic_surrogate_params *s);
+ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generations,
+                                  const ebic_evolve_params *params,
+                                  const ebic_surrogate_params *sp, ebic_result **out);
+
 /* Message of the last error on ctx.  With ctx == NULL: the calling thread's
  * last error from a call that had no context (ebic_create*, argument errors
  * of ebic_evolve*, ebic_result_*); an evaluation failure inside

@@ -20,6 +20,7 @@ from .binding import (  # noqa: F401
     Mlp,
     Trend,
     evolve,
+    evolve_surrogate,
     evolve_with,
     make_params,
     mask_words,

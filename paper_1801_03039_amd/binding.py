@@ -663,3 +663,58 @@ class Mlp:
         _check(_mlp_train_step(self._h, o.ctypes.data, c.ctypes.data, B, t.ctypes.data,
                                ctypes.byref(loss)))
         return float(loss.value)
+
+
+# ------------------------------------------------------ surrogate-screened run --
+
+SURROGATE_FN = ctypes.CFUNCTYPE(None, _vp, _i32, _i32, _dbl, _dbl, _i32)
+
+
+class SurrogateParamsC(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("oversample", _i32), ("warmup_generations", _i32),
+                ("train_steps", _i32), ("replay_generations", _i32), ("min_rank_corr", _dbl),
+                ("mlp_seed", _u64), ("mlp", MlpConfig), ("on_surrogate", SURROGATE_FN),
+                ("user", _vp)]
+
+
+_surrogate_defaults = _sig("ebic_surrogate_defaults", None, [_P(SurrogateParamsC)])
+_evolve_surrogate = _sig("ebic_evolve_surrogate", _i32,
+                         [_vp, _u64, _i32, _P(EvolveParamsC), _P(SurrogateParamsC), _P(_vp)])
+EXPORTED += ["ebic_surrogate_defaults", "ebic_evolve_surrogate"]
+
+
+def evolve_surrogate(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
+                     on_generation: Optional[Callable[[Generation], None]] = None,
+                     on_surrogate: Optional[Callable[[dict], None]] = None, **surrogate) -> EvolveResult:
+    """Surrogate-screened EBIC run (``ebic_evolve_surrogate``).  Keyword
+    arguments override ebic_surrogate_defaults: oversample, warmup_generations,
+    train_steps, replay_generations, min_rank_corr, mlp_seed, lr, hidden,
+    embed_dim."""
+    sp = SurrogateParamsC()
+    _surrogate_defaults(ctypes.byref(sp))
+    for k in ("oversample", "warmup_generations", "train_steps", "replay_generations",
+              "min_rank_corr", "mlp_seed"):
+        if k in surrogate:
+            setattr(sp, k, surrogate.pop(k))
+    for k in ("lr", "hidden", "embed_dim"):
+        if k in surrogate:
+            setattr(sp.mlp, k, surrogate.pop(k))
+    if surrogate:
+        raise TypeError(f"unknown surrogate options {sorted(surrogate)}")
+    if on_surrogate is None:
+        scb = SURROGATE_FN()
+    else:
+        def _s(user, gen, screened, corr, loss, pool):
+            on_surrogate({"gen": int(gen), "screened": bool(screened), "rank_corr": float(corr),
+                          "loss": float(loss), "pool": int(pool)})
+        scb = SURROGATE_FN(_s)
+    sp.on_surrogate = scb
+    gcb = _gen_callback(on_generation)
+    p = _params_c(cfg, gcb)
+    res = _vp()
+    st = _evolve_surrogate(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations),
+                           ctypes.byref(p), ctypes.byref(sp), ctypes.byref(res))
+    if st != EBIC_OK:
+        msg = _last_error(ctx.handle).decode(errors="replace") or _last_error(None).decode(errors="replace")
+        raise EbicError(st, msg)
+    return _finish(res, ctx.n_rows)

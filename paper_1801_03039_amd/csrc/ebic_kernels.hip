@@ -416,11 +416,13 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
                 if (NEG) tf[u] = in ? tf[u] : 0;
             }
             if (NEG) {
-                // lt(q,p) is the complement of lt(p,q) unless the pair ties.
+                // lt(q,p) is the complement of lt(p,q) unless the pair ties;
+                // slots past the end of the series break nothing.
                 pp = p;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    ld[u] = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
+                    const uint64_t rev = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
+                    ld[u] = t + u < L ? rev : ~0ull;
                     pp = q[u];
                 }
             }

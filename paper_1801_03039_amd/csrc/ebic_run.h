@@ -437,8 +437,8 @@ class Run {
         return best;
     }
 
-    // Steps 2-3: elitism, penalties and novel children.
-    void breed() {
+    // Step 2: elites from the top-rank list, penalties of their columns.
+    void elitism() {
         const int32_t P = p_.population;
         const std::vector<TopEntry> &top = toprank_.entries();
         std::fill(penalty_.begin(), penalty_.end(), 0);
@@ -453,24 +453,34 @@ class Run {
             for (int32_t c : te.s) ++penalty_[(size_t)c];
         }
         first_ = n_e;
+    }
+
+    // One Step 3 draw into child_: tournament winner(s) and one operation.
+    void make_child() {
+        const int32_t ia = tournament();
+        const uint64_t u = rng_.below((uint64_t)wsum_);
+        int op = 0;
+        int64_t acc = 0;
+        for (op = 0; op < 5; ++op) {
+            acc += p_.op_weight[op];
+            if ((int64_t)u < acc) break;
+        }
+        if (op == OP_CROSSOVER) {
+            const int32_t ib = tournament();
+            crossover(rng_, prev_.series(ia), prev_.len(ia), prev_.series(ib), prev_.len(ib), p_,
+                      child_);
+        } else {
+            child_.assign(prev_.series(ia), prev_.series(ia) + prev_.len(ia));
+            mutate(rng_, child_, op, p_, M_);
+        }
+    }
+
+    // Steps 2-3: elitism, penalties and novel children.
+    void breed() {
+        elitism();
         int32_t hits = 0;
-        while (cur_.size() < P) {
-            const int32_t ia = tournament();
-            const uint64_t u = rng_.below((uint64_t)wsum_);
-            int op = 0;
-            int64_t acc = 0;
-            for (op = 0; op < 5; ++op) {
-                acc += p_.op_weight[op];
-                if ((int64_t)u < acc) break;
-            }
-            if (op == OP_CROSSOVER) {
-                const int32_t ib = tournament();
-                crossover(rng_, prev_.series(ia), prev_.len(ia), prev_.series(ib), prev_.len(ib),
-                          p_, child_);
-            } else {
-                child_.assign(prev_.series(ia), prev_.series(ia) + prev_.len(ia));
-                mutate(rng_, child_, op, p_, M_);
-            }
+        while (cur_.size() < p_.population) {
+            make_child();
             const int32_t L = (int32_t)child_.size();
             if (!tabu_.insert(child_.data(), L)) {
                 if (++hits > tabu_limit_) {
@@ -484,6 +494,59 @@ class Run {
         }
     }
 
+  public:
+    // Screened Steps 2-3 (offspring screening by a surrogate; not in the
+    // paper): after elitism, draw oversample x (P - elites) children exactly
+    // like Step 3 -- novel with respect to the tabu list and to each other,
+    // each adding to its columns' penalties -- then keep the P - elites
+    // children that `score` ranks highest (ties: earlier child first).  Only
+    // the kept children enter the tabu list.  A draw that repeats a known or
+    // pooled series is a hit; more than tabu_limit x oversample hits stop the
+    // run.  `score(pool)` returns one value per pooled child.
+    template <typename Scorer>
+    bool next_screened(int32_t oversample, Scorer &&score) {
+        if (gen_ == 0) {
+            initial();
+            return true;
+        }
+        if (gen_ > generations_ || stopped_) return false;
+        elitism();
+        const int32_t need = p_.population - first_;
+        const int64_t limit = (int64_t)tabu_limit_ * oversample;
+        pool_.clear();
+        Tabu pooled;
+        int64_t hits = 0;
+        while (pool_.size() < (int64_t)need * oversample) {
+            make_child();
+            const int32_t L = (int32_t)child_.size();
+            if (tabu_.contains(child_.data(), L) || !pooled.insert(child_.data(), L)) {
+                if (++hits > limit) {
+                    stopped_ = true;
+                    return false;
+                }
+                continue;
+            }
+            pool_.push(child_.data(), L);
+            for (int32_t c : child_) ++penalty_[(size_t)c];
+        }
+        std::vector<float> s = score(pool_);
+        std::vector<int32_t> order((size_t)pool_.size());
+        for (int32_t i = 0; i < pool_.size(); ++i) {
+            order[(size_t)i] = i;
+            if (s[(size_t)i] != s[(size_t)i]) s[(size_t)i] = -INFINITY;  // NaN ranks last
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return s[(size_t)a] > s[(size_t)b]; });
+        order.resize((size_t)need);
+        std::sort(order.begin(), order.end());
+        for (int32_t i : order) {
+            cur_.push(pool_.series(i), pool_.len(i));
+            tabu_.insert(pool_.series(i), pool_.len(i));
+        }
+        return true;
+    }
+
+  private:
     const ebic_evolve_params p_;
     const int32_t M_;
     const int32_t generations_;
@@ -491,7 +554,7 @@ class Run {
     Tabu tabu_;
     TopRank toprank_;
     std::vector<int32_t> penalty_, s_, child_;
-    Pop prev_, cur_;
+    Pop prev_, cur_, pool_;
     ebic_params evalp_{};
     int64_t wsum_ = 0;
     int32_t tabu_limit_ = 0;
