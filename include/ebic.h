@@ -325,6 +325,10 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
  * here, called with the run index, one call at a time).  host_threads <= 0
  * picks the hardware concurrency.  The launch shape is tuned on the first
  * generation unless set before. */
+/* Device time (ms) of the last batched launch: the run-table copy and the
+ * persistent kernel, from events on the batch's stream around the graph. */
+double ebic_batch_last_ms(const ebic_batch *b);
+
 typedef void (*ebic_batch_generation_fn)(void *user, int32_t run, int32_t gen,
                                          const int32_t *offsets, const int32_t *cols, int32_t P,
                                          const int32_t *counts, const double *fitness);
@@ -338,16 +342,18 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
  * learned per-column embeddings (not in the paper; it only ranks
  * candidates, every admitted candidate is still scored exactly).
  *
- *   x    = mean of the series' column embeddings E[c] (embed_dim each)
- *   h1   = relu(W1 bf16(x) + b1)        W1: hidden x embed_dim
+ *   x    = [ mean over the series of E[c_t] ;
+ *            mean over consecutive pairs of F[c_t] * T[c_{t+1}] (0 if L = 1) ]
+ *          (E, F, T: embed_dim each; the pair term makes the model see order)
+ *   h1   = relu(W1 bf16(x) + b1)        W1: hidden x (2 embed_dim)
  *   h2   = relu(W2 bf16(h1) + b2)       W2: hidden x hidden
  *   y    = w3 . bf16(h2) + b3           w3: hidden
  * Products use BF16 copies of the FP32 master weights on MFMA units with
  * FP32 accumulation; training minimises (1/B) sum (y - target)^2 with Adam
  * on the masters (gradients pass through the BF16 casts unchanged).
- * Parameters, flattened FP32 in this order: E [n_cols][embed_dim],
- * W1 [hidden][embed_dim], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
- * w3 [hidden], b3 [1].  All reductions run in a fixed order, so results are
+ * Parameters, flattened FP32 in this order: E, F, T [n_cols][embed_dim]
+ * each, W1 [hidden][2 embed_dim], b1 [hidden], W2 [hidden][hidden],
+ * b2 [hidden], w3 [hidden], b3 [1].  All reductions run in a fixed order, so results are
  * deterministic on a given device.  Errors: message via ebic_last_error(NULL).
  */
 typedef struct ebic_mlp ebic_mlp;
@@ -359,9 +365,9 @@ typedef struct {
 } ebic_mlp_config;
 
 void ebic_mlp_defaults(ebic_mlp_config *c);
-/* Parameters initialised from SplitMix64(seed): E ~ U(-1,1), W1 ~
- * U(+-sqrt(6/embed_dim)), W2 ~ U(+-sqrt(6/hidden)), w3 ~ U(+-sqrt(3/hidden)),
- * biases 0. */
+/* Parameters initialised from SplitMix64(seed): E, F, T ~ U(-1,1), W1 ~
+ * U(+-sqrt(6/(2 embed_dim))), W2 ~ U(+-sqrt(6/hidden)), w3 ~
+ * U(+-sqrt(3/hidden)), biases 0. */
 ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t seed,
                             int32_t device, ebic_mlp **out);
 ebic_status ebic_mlp_destroy(ebic_mlp *m);

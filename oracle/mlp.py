@@ -2,9 +2,10 @@
 
 TEST INFRASTRUCTURE (see ``oracle/__init__.py``).
 
-A 3-layer MLP over the mean of learned column embeddings, in float64:
+A 3-layer MLP over learned column embeddings, in float64:
 
-    x    = (1/L) sum_t E[c_t]
+    x    = [ (1/L) sum_t E[c_t] ;
+             (1/(L-1)) sum_{t<L-1} F[c_t] * T[c_{t+1}]  (0 when L = 1) ]
     z1   = W1 r(x) + b1,   h1 = relu(z1)
     z2   = W2 r(h1) + b2,  h2 = relu(z2)
     y    = w3 . r(h2) + b3
@@ -17,8 +18,8 @@ dW1 and dx) and treats every rounding as the identity (straight-through).
 With ``bf16=False`` the model is a plain float64 MLP, which the tests pin
 against central finite differences.
 
-Parameters are one flat vector: E [M][D], W1 [H][D], b1 [H], W2 [H][H],
-b2 [H], w3 [H], b3 [1].
+Parameters are one flat vector: E, F, T [M][D] each, W1 [H][2D], b1 [H],
+W2 [H][H], b2 [H], w3 [H], b3 [1].
 """
 from __future__ import annotations
 
@@ -40,8 +41,8 @@ def split(params, M, D, H):
     p = np.asarray(params, dtype=np.float64)
     i = 0
     out = {}
-    for name, shape in (("E", (M, D)), ("W1", (H, D)), ("b1", (H,)), ("W2", (H, H)),
-                        ("b2", (H,)), ("w3", (H,)), ("b3", (1,))):
+    for name, shape in (("E", (M, D)), ("F", (M, D)), ("T", (M, D)), ("W1", (H, 2 * D)),
+                        ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))):
         n = int(np.prod(shape))
         out[name] = p[i:i + n].reshape(shape)
         i += n
@@ -50,7 +51,7 @@ def split(params, M, D, H):
 
 
 def n_params(M, D, H):
-    return M * D + H * D + H + H * H + H + H + 1
+    return 3 * M * D + H * 2 * D + H + H * H + H + H + 1
 
 
 def _r(x, on):
@@ -63,10 +64,12 @@ def forward(params, offsets, cols, M, D, H, bf16=True):
     P = split(params, M, D, H)
     offsets = np.asarray(offsets)
     B = len(offsets) - 1
-    x = np.zeros((B, D))
+    x = np.zeros((B, 2 * D))
     for b in range(B):
         s = cols[offsets[b]:offsets[b + 1]]
-        x[b] = P["E"][s].sum(axis=0) / len(s)
+        x[b, :D] = P["E"][s].sum(axis=0) / len(s)
+        if len(s) > 1:
+            x[b, D:] = (P["F"][s[:-1]] * P["T"][s[1:]]).sum(axis=0) / (len(s) - 1)
     xr = _r(x, bf16)
     W1, W2, w3 = _r(P["W1"], bf16), _r(P["W2"], bf16), _r(P["w3"], bf16)
     z1 = xr @ W1.T + P["b1"]
@@ -74,7 +77,7 @@ def forward(params, offsets, cols, M, D, H, bf16=True):
     z2 = h1r @ W2.T + P["b2"]
     h2r = _r(np.maximum(z2, 0.0), bf16)
     y = h2r @ w3 + P["b3"][0]
-    return y, dict(x=x, xr=xr, z1=z1, h1r=h1r, z2=z2, h2r=h2r, W1=W1, W2=W2, w3=w3)
+    return y, dict(x=x, xr=xr, z1=z1, h1r=h1r, z2=z2, h2r=h2r, W1=W1, W2=W2, w3=w3, P=P)
 
 
 def loss_and_grad(params, offsets, cols, target, M, D, H, bf16=True):
@@ -96,11 +99,16 @@ def loss_and_grad(params, offsets, cols, target, M, D, H, bf16=True):
     dz1r = _r(dz1, bf16)
     g_W1 = dz1r.T @ c["xr"]
     dx = dz1r @ c["W1"]
-    g_E = np.zeros((M, D))
+    P = c["P"]
+    g_E, g_F, g_T = np.zeros((M, D)), np.zeros((M, D)), np.zeros((M, D))
     for b in range(B):
         s = cols[offsets[b]:offsets[b + 1]]
-        g_E[s] += dx[b] / len(s)
-    grad = np.concatenate([g_E.ravel(), g_W1.ravel(), g_b1, g_W2.ravel(), g_b2, g_w3, g_b3])
+        np.add.at(g_E, s, dx[b, :D] / len(s))
+        if len(s) > 1:
+            np.add.at(g_F, s[:-1], dx[b, D:] * P["T"][s[1:]] / (len(s) - 1))
+            np.add.at(g_T, s[1:], dx[b, D:] * P["F"][s[:-1]] / (len(s) - 1))
+    grad = np.concatenate([g_E.ravel(), g_F.ravel(), g_T.ravel(), g_W1.ravel(), g_b1,
+                           g_W2.ravel(), g_b2, g_w3, g_b3])
     return loss, grad, y
 
 

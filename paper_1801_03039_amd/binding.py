@@ -458,7 +458,8 @@ _batch_evaluate = _sig("ebic_batch_evaluate", _i32,
                        [_vp, _vp, _vp, _vp, _P(Params), _vp, _vp, _vp, _i32])
 _batch_evolve = _sig("ebic_batch_evolve", _i32,
                      [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _i32, _vp])
-EXPORTED += ["ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
+_batch_last_ms = _sig("ebic_batch_last_ms", _dbl, [_vp])
+EXPORTED += ["ebic_batch_last_ms", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
              "ebic_batch_set_tuning", "ebic_batch_evaluate", "ebic_batch_evolve"]
 
 
@@ -500,6 +501,10 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+    def last_ms(self) -> float:
+        """Device time of the last batched launch (run-table copy + kernel)."""
+        return float(_batch_last_ms(self._h))
 
     def tuning(self) -> dict:
         t = BatchTuning()

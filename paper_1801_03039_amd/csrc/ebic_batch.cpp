@@ -53,6 +53,8 @@ struct ebic_batch {
     bool tuned = false;
     hipGraphExec_t exec = nullptr;
     BatchLaunch graph_key{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the last graph launch
+    double last_ms = 0.0;
 };
 
 namespace {
@@ -229,8 +231,10 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),
                         hipMemcpyHostToDevice, b->stream));
+    BHIP(hipEventRecord(b->ev0, b->stream));
     ebic_status st = launch_graph(b, make_launch(b, q, std::max(1, workgroups), unroll));
     if (st != EBIC_OK) return st;
+    BHIP(hipEventRecord(b->ev1, b->stream));
     if (copy_back) {
         BHIP(hipMemcpyAsync(b->h_counts, b->d_counts, sizeof(int32_t) * (size_t)q.n_cand,
                             hipMemcpyDeviceToHost, b->stream));
@@ -238,6 +242,9 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
                             hipMemcpyDeviceToHost, b->stream));
     }
     BHIP(hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    b->last_ms = ms;
     return EBIC_OK;
 }
 
@@ -349,6 +356,8 @@ ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, cons
     }
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e != hipSuccess) return cleanup(bhip(e, "batch stream"));
     if ((e = hipMalloc((void **)&b->d_runs, sizeof(IndexRun) * (size_t)n_runs)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_tile_base, sizeof(uint32_t) * ((size_t)n_runs + 1))) !=
@@ -382,11 +391,15 @@ ebic_status ebic_batch_destroy(ebic_batch *b) {
     void *host[] = {b->h_runs, b->h_tile_base, b->h_off, b->h_cols, b->h_counts, b->h_fit};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     for (ebic_ctx *c : b->ctx) ebic_destroy(c);
     delete b;
     return EBIC_OK;
 }
+
+double ebic_batch_last_ms(const ebic_batch *b) { return b ? b->last_ms : 0.0; }
 
 ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
     if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))

@@ -25,13 +25,14 @@ struct ebic_mlp {
     int32_t M = 0, D = 0, H = 0;
     ebic_mlp_config cfg{};
     int64_t n_params = 0;
-    int64_t oE = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, ow3 = 0, ob3 = 0;
+    int64_t oE = 0, oF = 0, oT = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, ow3 = 0, ob3 = 0;
     float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
     uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;
     int64_t step = 0;
     // per-batch buffers (capacity cap_B candidates, cap_L column entries)
     int64_t cap_B = 0, cap_L = 0;
-    int32_t *off = nullptr, *cols = nullptr, *occ_start = nullptr, *occ_b = nullptr;
+    int32_t *off = nullptr, *cols = nullptr, *occ_start = nullptr, *occ_pos = nullptr,
+            *occ_b = nullptr;
     float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *y = nullptr, *t = nullptr, *dy = nullptr,
           *sq = nullptr, *dZ2 = nullptr, *G1 = nullptr, *dZ1 = nullptr, *dX = nullptr;
     uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
@@ -72,8 +73,8 @@ ebic_status reserve(ebic_mlp *m, int64_t B, int64_t L) {
         MHIP(hipStreamSynchronize(m->stream));
         const int64_t c = std::max<int64_t>(B, m->cap_B * 2);
         MHIP(dalloc(m->off, c + 1));
-        MHIP(dalloc(m->X, c * D));
-        MHIP(dalloc(m->Xb, c * D));
+        MHIP(dalloc(m->X, c * 2 * D));
+        MHIP(dalloc(m->Xb, c * 2 * D));
         MHIP(dalloc(m->Z1, c * H));
         MHIP(dalloc(m->H1b, c * H));
         MHIP(dalloc(m->Z2, c * H));
@@ -87,17 +88,18 @@ ebic_status reserve(ebic_mlp *m, int64_t B, int64_t L) {
         MHIP(dalloc(m->G1, c * H));
         MHIP(dalloc(m->dZ1, c * H));
         MHIP(dalloc(m->dZ1b, c * H));
-        MHIP(dalloc(m->dX, c * D));
+        MHIP(dalloc(m->dX, c * 2 * D));
         m->cap_B = c;
     }
     if (L > m->cap_L) {
         MHIP(hipStreamSynchronize(m->stream));
         const int64_t c = std::max<int64_t>(L, m->cap_L * 2);
         MHIP(dalloc(m->cols, c));
+        MHIP(dalloc(m->occ_pos, c));
         MHIP(dalloc(m->occ_b, c));
         m->cap_L = c;
     }
-    const int64_t need_ws = (int64_t)kMaxSplits * std::max<int64_t>(H * H, H * D);
+    const int64_t need_ws = (int64_t)kMaxSplits * std::max<int64_t>(H * H, H * 2 * D);
     if (need_ws > m->cap_ws) {
         MHIP(dalloc(m->ws, need_ws));
         m->cap_ws = need_ws;
@@ -133,17 +135,23 @@ ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t
         MHIP(hipMemcpyAsync(m->t, target, sizeof(float) * (size_t)B, hipMemcpyHostToDevice,
                             m->stream));
     if (occurrences) {
-        // CSR by column: every occurrence of column j, candidates in order.
-        std::vector<int32_t> start((size_t)m->M + 1, 0), occ((size_t)L);
+        // CSR by column: every occurrence (position in cols, and its
+        // candidate) of column j, in candidate-then-series order.
+        std::vector<int32_t> start((size_t)m->M + 1, 0), pos((size_t)L), occ((size_t)L);
         for (int64_t i = 0; i < L; ++i) ++start[(size_t)cols[i] + 1];
         for (int32_t j = 0; j < m->M; ++j) start[(size_t)j + 1] += start[(size_t)j];
         std::vector<int32_t> fill(start.begin(), start.end() - 1);
         for (int32_t b = 0; b < B; ++b)
-            for (int32_t i = off[b]; i < off[b + 1]; ++i) occ[(size_t)fill[(size_t)cols[i]]++] = b;
+            for (int32_t i = off[b]; i < off[b + 1]; ++i) {
+                const int32_t k = fill[(size_t)cols[i]]++;
+                pos[(size_t)k] = i;
+                occ[(size_t)k] = b;
+            }
         if (!m->occ_start) MHIP(hipMalloc((void **)&m->occ_start, sizeof(int32_t) * ((size_t)m->M + 1)));
         MHIP(hipStreamSynchronize(m->stream));  // no kernel still reads the previous lists
         MHIP(hipMemcpy(m->occ_start, start.data(), sizeof(int32_t) * start.size(),
                        hipMemcpyHostToDevice));
+        MHIP(hipMemcpy(m->occ_pos, pos.data(), sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice));
         MHIP(hipMemcpy(m->occ_b, occ.data(), sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice));
     }
     return EBIC_OK;
@@ -152,8 +160,10 @@ ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t
 ebic_status forward(ebic_mlp *m, int32_t B) {
     const int32_t D = m->D, H = m->H;
     hipStream_t s = m->stream;
-    MHIP(mlp::pool_fwd(m->p + m->oE, D, m->off, m->cols, B, m->X, m->Xb, s));
-    mlp::Gemm l1{m->Xb, D, 1, m->W1b, 1, D, B, H, D, 1, m->p + m->ob1, 1, m->Z1, m->H1b, nullptr};
+    const int32_t D2 = 2 * D;
+    MHIP(mlp::pool_fwd(m->p + m->oE, m->p + m->oF, m->p + m->oT, D, m->off, m->cols, B, m->X,
+                       m->Xb, s));
+    mlp::Gemm l1{m->Xb, D2, 1, m->W1b, 1, D2, B, H, D2, 1, m->p + m->ob1, 1, m->Z1, m->H1b, nullptr};
     MHIP(mlp::gemm(l1, s));
     mlp::Gemm l2{m->H1b, H, 1, m->W2b, 1, H, B, H, H, 1, m->p + m->ob2, 1, m->Z2, m->H2b, nullptr};
     MHIP(mlp::gemm(l2, s));
@@ -163,7 +173,7 @@ ebic_status forward(ebic_mlp *m, int32_t B) {
 
 // Gradients of the mean squared error into m->g (layout of the parameters).
 ebic_status backward(ebic_mlp *m, int32_t B) {
-    const int32_t D = m->D, H = m->H, S = splits_for(B);
+    const int32_t D = m->D, D2 = 2 * m->D, H = m->H, S = splits_for(B);
     hipStream_t s = m->stream;
     float *g = m->g;
     MHIP(mlp::loss(m->y, m->t, B, m->dy, m->sq, s));
@@ -180,17 +190,18 @@ ebic_status backward(ebic_mlp *m, int32_t B) {
     MHIP(mlp::relu_bwd(m->G1, m->Z1, (int64_t)B * H, m->dZ1, m->dZ1b, s));
     MHIP(mlp::colsum(m->dZ1, nullptr, B, H, S, m->ws, g + m->ob1, s));
     // dW1[h][d] = sum_b dZ1[b][h] x[b][d]
-    mlp::Gemm gw1{m->dZ1b, 1, H, m->Xb, D, 1, H, D, B, S, nullptr, 0, g + m->oW1, nullptr, m->ws};
+    mlp::Gemm gw1{m->dZ1b, 1, H, m->Xb, D2, 1, H, D2, B, S, nullptr, 0, g + m->oW1, nullptr, m->ws};
     MHIP(mlp::gemm(gw1, s));
     // dX[b][d] = sum_h dZ1[b][h] W1[h][d]
-    mlp::Gemm gx{m->dZ1b, H, 1, m->W1b, D, 1, B, D, H, 1, nullptr, 0, m->dX, nullptr, nullptr};
+    mlp::Gemm gx{m->dZ1b, H, 1, m->W1b, D2, 1, B, D2, H, 1, nullptr, 0, m->dX, nullptr, nullptr};
     MHIP(mlp::gemm(gx, s));
-    MHIP(mlp::pool_bwd(m->dX, D, m->off, m->occ_start, m->occ_b, m->M, g + m->oE, s));
+    MHIP(mlp::pool_bwd(m->dX, D, m->p + m->oF, m->p + m->oT, m->off, m->cols, m->occ_start,
+                       m->occ_pos, m->occ_b, m->M, g + m->oE, g + m->oF, g + m->oT, s));
     return EBIC_OK;
 }
 
 ebic_status refresh_bf16(ebic_mlp *m) {
-    MHIP(mlp::cast_bf16(m->p + m->oW1, (int64_t)m->H * m->D, m->W1b, m->stream));
+    MHIP(mlp::cast_bf16(m->p + m->oW1, (int64_t)m->H * 2 * m->D, m->W1b, m->stream));
     MHIP(mlp::cast_bf16(m->p + m->oW2, (int64_t)m->H * m->H, m->W2b, m->stream));
     MHIP(mlp::cast_bf16(m->p + m->ow3, (int64_t)m->H, m->w3b, m->stream));
     return EBIC_OK;
@@ -247,8 +258,10 @@ ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t
     m->cfg = *cfg;
     const int64_t M = n_cols, D = m->D, H = m->H;
     m->oE = 0;
-    m->oW1 = m->oE + M * D;
-    m->ob1 = m->oW1 + H * D;
+    m->oF = m->oE + M * D;
+    m->oT = m->oF + M * D;
+    m->oW1 = m->oT + M * D;
+    m->ob1 = m->oW1 + H * 2 * D;
     m->oW2 = m->ob1 + H;
     m->ob2 = m->oW2 + H * H;
     m->ow3 = m->ob2 + H;
@@ -256,8 +269,9 @@ ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t
     m->n_params = m->ob3 + 1;
     std::vector<float> init((size_t)m->n_params, 0.f);
     SplitMix rng{seed};
-    for (int64_t i = 0; i < M * D; ++i) init[(size_t)(m->oE + i)] = rng.sym(1.f);
-    for (int64_t i = 0; i < H * D; ++i) init[(size_t)(m->oW1 + i)] = rng.sym(std::sqrt(6.f / D));
+    for (int64_t i = 0; i < 3 * M * D; ++i) init[(size_t)(m->oE + i)] = rng.sym(1.f);
+    for (int64_t i = 0; i < H * 2 * D; ++i)
+        init[(size_t)(m->oW1 + i)] = rng.sym(std::sqrt(6.f / (2 * D)));
     for (int64_t i = 0; i < H * H; ++i) init[(size_t)(m->oW2 + i)] = rng.sym(std::sqrt(6.f / H));
     for (int64_t i = 0; i < H; ++i) init[(size_t)(m->ow3 + i)] = rng.sym(std::sqrt(3.f / H));
     auto fail = [&](hipError_t e, const char *w) {
@@ -271,7 +285,7 @@ ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t
     if (e == hipSuccess) e = dalloc(m->g, m->n_params);
     if (e == hipSuccess) e = dalloc(m->m1, m->n_params);
     if (e == hipSuccess) e = dalloc(m->m2, m->n_params);
-    if (e == hipSuccess) e = dalloc(m->W1b, H * D);
+    if (e == hipSuccess) e = dalloc(m->W1b, H * 2 * D);
     if (e == hipSuccess) e = dalloc(m->W2b, H * H);
     if (e == hipSuccess) e = dalloc(m->w3b, H);
     if (e != hipSuccess) return fail(e, "model buffers");
@@ -289,7 +303,7 @@ ebic_status ebic_mlp_destroy(ebic_mlp *m) {
     (void)hipSetDevice(m->device);
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     void *bufs[] = {m->p, m->g, m->m1, m->m2, m->W1b, m->W2b, m->w3b, m->off, m->cols,
-                    m->occ_start, m->occ_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
+                    m->occ_start, m->occ_pos, m->occ_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
                     m->dZ2, m->G1, m->dZ1, m->dX, m->Xb, m->H1b, m->H2b, m->dZ2b, m->dZ1b, m->ws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

@@ -25,10 +25,12 @@ struct Gemm {
     float *ws;             // splits > 1
 };
 
-hipError_t pool_fwd(const float *E, int32_t D, const int32_t *off, const int32_t *cols, int32_t B,
-                    float *X, uint16_t *Xb, hipStream_t s);
-hipError_t pool_bwd(const float *dX, int32_t D, const int32_t *off, const int32_t *occ_start,
-                    const int32_t *occ_b, int32_t M, float *dE, hipStream_t s);
+hipError_t pool_fwd(const float *E, const float *F, const float *T, int32_t D, const int32_t *off,
+                    const int32_t *cols, int32_t B, float *X, uint16_t *Xb, hipStream_t s);
+hipError_t pool_bwd(const float *dX, int32_t D, const float *F, const float *T, const int32_t *off,
+                    const int32_t *cols, const int32_t *occ_start, const int32_t *occ_pos,
+                    const int32_t *occ_b, int32_t M, float *dE, float *dF, float *dT,
+                    hipStream_t s);
 hipError_t gemm(const Gemm &g, hipStream_t s);
 hipError_t colsum(const float *X, const float *w, int32_t B, int32_t N, int32_t splits, float *ws,
                   float *out, hipStream_t s);

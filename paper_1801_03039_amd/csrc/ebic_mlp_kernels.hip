@@ -1,7 +1,8 @@
 // Surrogate fitness model: a 3-layer MLP over learned column embeddings,
 // trained and run on gfx950 with hand-written kernels.
 //
-//   x_b  = (1/L_b) * sum_t E[c_{b,t}]                 embedding mean pool (FP32)
+//   x_b  = [ (1/L) sum_t E[c_t] ;                     node embeddings, mean pool
+//            (1/(L-1)) sum_{t<L-1} F[c_t] * T[c_{t+1}] ]   ordered pairs (0 if L = 1)
 //   z1   = W1 bf16(x_b) + b1,  h1 = relu(z1)          BF16 MFMA, FP32 accumulate
 //   z2   = W2 bf16(h1) + b2,   h2 = relu(z2)          BF16 MFMA, FP32 accumulate
 //   y_b  = w3 . bf16(h2) + b3                         FP32 accumulate
@@ -39,39 +40,72 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 // ------------------------------------------------------------ embedding --
 
-// X[b][d] = (sum_t E[c_t][d]) / L_b, summed in series order; Xb = bf16(X).
-__global__ __launch_bounds__(kBlock) void pool_fwd_kernel(const float *__restrict__ E, int32_t D,
+// X[b][d] for d < D: (sum_t E[c_t][d]) / L; for d = D + e:
+// (sum_{t < L-1} F[c_t][e] * T[c_{t+1}][e]) / (L - 1), 0 when L = 1; sums in
+// series order.  Xb = bf16(X).  X is B x 2D.
+__global__ __launch_bounds__(kBlock) void pool_fwd_kernel(const float *__restrict__ E,
+                                                          const float *__restrict__ F,
+                                                          const float *__restrict__ T, int32_t D,
                                                           const int32_t *__restrict__ off,
                                                           const int32_t *__restrict__ cols,
                                                           int32_t B, float *__restrict__ X,
                                                           uint16_t *__restrict__ Xb) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= (int64_t)B * D) return;
-    const int32_t b = (int32_t)(i / D), d = (int32_t)(i - (int64_t)b * D);
+    const int32_t D2 = 2 * D;
+    if (i >= (int64_t)B * D2) return;
+    const int32_t b = (int32_t)(i / D2), d = (int32_t)(i - (int64_t)b * D2);
     const int32_t s = off[b], e = off[b + 1];
-    float acc = 0.f;
-    for (int32_t t = s; t < e; ++t) acc += E[(int64_t)cols[t] * D + d];
-    const float x = acc / (float)(e - s);
+    float x = 0.f;
+    if (d < D) {
+        float acc = 0.f;
+        for (int32_t t = s; t < e; ++t) acc += E[(int64_t)cols[t] * D + d];
+        x = acc / (float)(e - s);
+    } else if (e - s > 1) {
+        const int32_t dd = d - D;
+        float acc = 0.f;
+        for (int32_t t = s; t + 1 < e; ++t)
+            acc += F[(int64_t)cols[t] * D + dd] * T[(int64_t)cols[t + 1] * D + dd];
+        x = acc / (float)(e - s - 1);
+    }
     X[i] = x;
     Xb[i] = to_bf16(x);
 }
 
-// dE[j][d] = sum over occurrences (b) of column j, in list order, of
-// dX[b][d] / L_b.  The occurrence lists (CSR by column) come from the host.
+// Gradients of the three embedding tables for column j, gathered over its
+// occurrences (positions in cols, in candidate-then-series order, with their
+// candidate in occ_b) so that every sum has a fixed order:
+//   dE[j] += dX[b][0:D] / L
+//   dF[j] += dX[b][D:2D] * T[next column] / (L-1)   (j not last)
+//   dT[j] += dX[b][D:2D] * F[previous column] / (L-1) (j not first)
 __global__ __launch_bounds__(kBlock) void pool_bwd_kernel(const float *__restrict__ dX, int32_t D,
+                                                          const float *__restrict__ F,
+                                                          const float *__restrict__ T,
                                                           const int32_t *__restrict__ off,
+                                                          const int32_t *__restrict__ cols,
                                                           const int32_t *__restrict__ occ_start,
+                                                          const int32_t *__restrict__ occ_pos,
                                                           const int32_t *__restrict__ occ_b,
-                                                          int32_t M, float *__restrict__ dE) {
+                                                          int32_t M, float *__restrict__ dE,
+                                                          float *__restrict__ dF,
+                                                          float *__restrict__ dT) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= (int64_t)M * D) return;
     const int32_t j = (int32_t)(i / D), d = (int32_t)(i - (int64_t)j * D);
-    float acc = 0.f;
+    float ge = 0.f, gf = 0.f, gt = 0.f;
     for (int32_t o = occ_start[j]; o < occ_start[j + 1]; ++o) {
-        const int32_t b = occ_b[o];
-        acc += dX[(int64_t)b * D + d] / (float)(off[b + 1] - off[b]);
+        const int32_t pos = occ_pos[o], b = occ_b[o];
+        const int32_t s = off[b], e = off[b + 1];
+        const float *dx = dX + (int64_t)b * 2 * D;
+        ge += dx[d] / (float)(e - s);
+        if (e - s > 1) {
+            const float inv = 1.f / (float)(e - s - 1);
+            if (pos + 1 < e) gf += dx[D + d] * T[(int64_t)cols[pos + 1] * D + d] * inv;
+            if (pos > s) gt += dx[D + d] * F[(int64_t)cols[pos - 1] * D + d] * inv;
+        }
     }
-    dE[i] = acc;
+    dE[i] = ge;
+    dF[i] = gf;
+    dT[i] = gt;
 }
 
 // ----------------------------------------------------------------- GEMM --
@@ -309,17 +343,19 @@ inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)
 
 // ----------------------------------------------------------- launchers --
 
-hipError_t pool_fwd(const float *E, int32_t D, const int32_t *off, const int32_t *cols, int32_t B,
-                    float *X, uint16_t *Xb, hipStream_t s) {
-    hipLaunchKernelGGL(pool_fwd_kernel, grid1((int64_t)B * D), dim3(kBlock), 0, s, E, D, off, cols,
-                       B, X, Xb);
+hipError_t pool_fwd(const float *E, const float *F, const float *T, int32_t D, const int32_t *off,
+                    const int32_t *cols, int32_t B, float *X, uint16_t *Xb, hipStream_t s) {
+    hipLaunchKernelGGL(pool_fwd_kernel, grid1((int64_t)B * 2 * D), dim3(kBlock), 0, s, E, F, T, D,
+                       off, cols, B, X, Xb);
     return hipGetLastError();
 }
 
-hipError_t pool_bwd(const float *dX, int32_t D, const int32_t *off, const int32_t *occ_start,
-                    const int32_t *occ_b, int32_t M, float *dE, hipStream_t s) {
-    hipLaunchKernelGGL(pool_bwd_kernel, grid1((int64_t)M * D), dim3(kBlock), 0, s, dX, D, off,
-                       occ_start, occ_b, M, dE);
+hipError_t pool_bwd(const float *dX, int32_t D, const float *F, const float *T, const int32_t *off,
+                    const int32_t *cols, const int32_t *occ_start, const int32_t *occ_pos,
+                    const int32_t *occ_b, int32_t M, float *dE, float *dF, float *dT,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(pool_bwd_kernel, grid1((int64_t)M * D), dim3(kBlock), 0, s, dX, D, F, T,
+                       off, cols, occ_start, occ_pos, occ_b, M, dE, dF, dT);
     return hipGetLastError();
 }
 

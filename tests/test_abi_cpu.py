@@ -65,7 +65,9 @@ def test_one_hip_runtime_per_process():
     # (same SONAME), never bring in a second one.
     import subprocess
     import sys
-    code = ("import paper_1801_03039_amd, torch\n"
+    code = ("import paper_1801_03039_amd as e\n"
+            "e.Context  # loads libebic.so\n"
+            "import torch\n"
             "maps = open('/proc/self/maps').read().splitlines()\n"
             "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
             "print(len(libs), libs)\n")

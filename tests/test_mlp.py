@@ -34,7 +34,8 @@ def _batch(rng, M, B, lmin=1, lmax=12):
 
 
 def _blocks(M, D, H):
-    sizes = [("E", M * D), ("W1", H * D), ("b1", H), ("W2", H * H), ("b2", H), ("w3", H), ("b3", 1)]
+    sizes = [("E", M * D), ("F", M * D), ("T", M * D), ("W1", H * 2 * D), ("b1", H), ("W2", H * H),
+             ("b2", H), ("w3", H), ("b3", 1)]
     out, i = {}, 0
     for n, s in sizes:
         out[n] = slice(i, i + s)
