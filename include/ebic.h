@@ -418,6 +418,56 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
                                   const ebic_evolve_params *params,
                                   const ebic_surrogate_params *sp, ebic_result **out);
 
+/*
+ * Step 6 output on the device: the indices of the rows each bicluster
+ * matches, from its 64-row masks (bit r mod 64 of word r / 64, as written by
+ * ebic_evaluate*).  d_masks: [K][planes][W] words, W = ebic_mask_words(n_rows);
+ * the planes of a bicluster are united (planes = 2 takes both trend
+ * directions of ebic_evaluate's masks); bits at or beyond n_rows are not
+ * rows.  Outputs (device, caller-owned): d_offsets [K + 1] int64 with
+ * d_offsets[0] = 0 and bicluster k's rows at d_rows[d_offsets[k] ..
+ * d_offsets[k + 1]), increasing; entries at or beyond rows_capacity are not
+ * written, so a caller that sizes d_rows after reading d_offsets[K] (or
+ * passes n_rows * K) gets every list.  Stream-ordered on hip_stream (NULL:
+ * the HIP null stream); allocates nothing.  Errors: E_ARG (negative sizes,
+ * null pointers, n_rows > INT32_MAX), E_DEVICE (launch), message via
+ * ebic_last_error(NULL).
+ */
+ebic_status ebic_mask_rows(const uint64_t *d_masks, int32_t K, int32_t planes, int64_t n_rows,
+                           int64_t *d_offsets, int32_t *d_rows, int64_t rows_capacity,
+                           void *hip_stream);
+
+/* A set of biclusters in device memory: rows as masks [count][planes][W]
+ * (planes united, as in ebic_mask_rows), columns as CBF (col_offsets
+ * [count + 1], cols).  Column order does not matter here; repeated columns
+ * count once. */
+typedef struct {
+    uint32_t struct_size;        /* sizeof(ebic_bicluster_set) */
+    int32_t count;
+    int32_t planes;
+    const uint64_t *row_masks;
+    const int32_t *col_offsets;
+    const int32_t *cols;
+} ebic_bicluster_set;
+
+/*
+ * Accuracy of found biclusters against expected ones (Section 3, Eqs. 2-3)
+ * on the device.  Each bicluster is the set of cells rows x columns; the
+ * Jaccard index of two is |intersection| / |union| of their cells (0 when
+ * both are empty).  d_jaccard [found->count][expected->count] (FP64,
+ * row-major; may be NULL only if either count is 0) receives every index;
+ * d_scores[0] = recovery = mean over expected e of max over found f of
+ * J[f][e], d_scores[1] = relevance = mean over found f of max over expected
+ * e of J[f][e] (both 0 when either set is empty).  The paper prints the two
+ * as bare sums and reports shares; we divide by the set sizes.  Sums are
+ * taken in index order, so results are deterministic.  Stream-ordered on
+ * hip_stream; allocates nothing.  Errors: E_ARG (bad set descriptions, null
+ * outputs, more than 2^33 pairs), E_DEVICE; message via ebic_last_error(NULL).
+ */
+ebic_status ebic_match_scores(const ebic_bicluster_set *found, const ebic_bicluster_set *expected,
+                              int64_t n_rows, double *d_jaccard, double *d_scores,
+                              void *hip_stream);
+
 /* Message of the last error on ctx.  With ctx == NULL: the calling thread's
  * last error from a call that had no context (ebic_create*, argument errors
  * of ebic_evolve*, ebic_result_*); an evaluation failure inside

@@ -5,7 +5,8 @@
 fitness and optionally row masks) with the HIP kernels of ``libebic.so``.
 ``evolve`` runs EBIC on a context, ``Batch`` evaluates or evolves many
 matrices together, ``Mlp`` and ``evolve_surrogate`` provide the surrogate
-screen.
+screen, ``mask_rows`` and ``match_scores`` give Step 6's row lists and the
+recovery / relevance scores on the device.
 
 The names below are loaded from the compiled library on first use (so that
 ``python -m paper_1801_03039_amd.build`` works whatever is built); there is no
@@ -14,7 +15,8 @@ CPU fallback: using them without a built library raises ``ImportError``.
 _EXPORTS = (
     "Batch", "Context", "EbicError", "EBIC_PATH_AUTO", "EBIC_PATH_DIRECT", "EBIC_PATH_INDEX",
     "LIB_PATH", "EvolveConfig", "EvolveResult", "Generation", "Mlp", "Trend", "evolve",
-    "evolve_surrogate", "evolve_with", "make_params", "mask_words", "binding",
+    "evolve_surrogate", "evolve_with", "make_params", "mask_words", "mask_rows",
+    "match_scores", "binding",
 )
 
 __all__ = list(_EXPORTS)

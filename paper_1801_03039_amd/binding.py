@@ -723,3 +723,102 @@ def evolve_surrogate(ctx: Context, seed: int, generations: int, cfg: EvolveConfi
         msg = _last_error(ctx.handle).decode(errors="replace") or _last_error(None).decode(errors="replace")
         raise EbicError(st, msg)
     return _finish(res, ctx.n_rows)
+
+
+# ------------------------------------------------- Step 6 rows and accuracy --
+
+class BiclusterSetC(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("count", _i32), ("planes", _i32), ("row_masks", _vp),
+                ("col_offsets", _vp), ("cols", _vp)]
+
+
+_mask_rows = _sig("ebic_mask_rows", _i32, [_vp, _i32, _i32, _i64, _vp, _vp, _i64, _vp])
+_match_scores = _sig("ebic_match_scores", _i32,
+                     [_P(BiclusterSetC), _P(BiclusterSetC), _i64, _vp, _vp, _vp])
+EXPORTED += ["ebic_mask_rows", "ebic_match_scores"]
+
+
+def _dev_check(t, name, dtype, stream):
+    import torch as _t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+def _mask_shape(masks, n_rows: int):
+    """[K][W] or [K][planes][W] 64-bit masks -> (K, planes)."""
+    W = mask_words(n_rows)
+    if masks.element_size() != 8:
+        raise TypeError("masks must hold 64-bit words")
+    if masks.dim() == 2:
+        K, planes, w = masks.shape[0], 1, masks.shape[1]
+    elif masks.dim() == 3:
+        K, planes, w = masks.shape
+    else:
+        raise ValueError("masks must be [K][W] or [K][planes][W]")
+    if w != W:
+        raise ValueError(f"masks hold {w} words per plane, n_rows needs {W}")
+    return int(K), int(planes)
+
+
+def mask_rows(masks, n_rows: int, capacity: Optional[int] = None, stream=None):
+    """Row indices of each bicluster (``ebic_mask_rows``) from device masks
+    [K][W] or [K][planes][W] (planes united).  Returns device tensors
+    (offsets int64 [K+1], rows int32 [capacity]); with capacity None the
+    offsets are read back first and rows is sized to hold every list."""
+    import torch as _t
+    if not masks.is_cuda or not masks.is_contiguous():
+        raise ValueError("masks must be a contiguous device tensor")
+    K, planes = _mask_shape(masks, n_rows)
+    dev = masks.device
+    if stream is None:
+        stream = _t.cuda.current_stream(dev)
+    offsets = _t.empty(K + 1, dtype=_t.int64, device=dev)
+    size_first = capacity is None
+    cap = 0 if size_first else int(capacity)
+    rows = _t.empty(max(cap, 1), dtype=_t.int32, device=dev)
+    args = [_vp(masks.data_ptr()), K, planes, int(n_rows), _vp(offsets.data_ptr()),
+            _vp(rows.data_ptr()), cap, _vp(stream.cuda_stream)]
+    _check(_mask_rows(*args))
+    if size_first:
+        stream.synchronize()
+        cap = int(offsets[-1].item())
+        rows = _t.empty(max(cap, 1), dtype=_t.int32, device=dev)
+        args[5], args[6] = _vp(rows.data_ptr()), cap
+        _check(_mask_rows(*args))
+    return offsets, rows[:cap]
+
+
+def _set_c(s, n_rows, keep):
+    import torch as _t
+    masks, col_off, cols = s
+    K, planes = _mask_shape(masks, n_rows)
+    _dev_check(masks, "row masks", masks.dtype, None)
+    _dev_check(col_off, "col_offsets", _t.int32, None)
+    _dev_check(cols, "cols", _t.int32, None)
+    if col_off.numel() != K + 1:
+        raise ValueError("col_offsets must hold count + 1 entries")
+    keep.extend([masks, col_off, cols])
+    return BiclusterSetC(ctypes.sizeof(BiclusterSetC), K, planes, _vp(masks.data_ptr()),
+                         _vp(col_off.data_ptr()), _vp(cols.data_ptr()))
+
+
+def match_scores(found, expected, n_rows: int, stream=None):
+    """Recovery and relevance (``ebic_match_scores``).  found / expected:
+    (row masks [K][W] or [K][planes][W], col_offsets int32 [K+1], cols int32)
+    device tensors.  Returns (J [F][E] float64 device tensor, recovery,
+    relevance)."""
+    import torch as _t
+    keep = []
+    fc, ec = _set_c(found, n_rows, keep), _set_c(expected, n_rows, keep)
+    dev = found[0].device
+    if stream is None:
+        stream = _t.cuda.current_stream(dev)
+    J = _t.empty((fc.count, ec.count), dtype=_t.float64, device=dev)
+    scores = _t.empty(2, dtype=_t.float64, device=dev)
+    _check(_match_scores(ctypes.byref(fc), ctypes.byref(ec), int(n_rows),
+                         _vp(J.data_ptr()) if J.numel() else None, _vp(scores.data_ptr()),
+                         _vp(stream.cuda_stream)))
+    s = scores.cpu().numpy()
+    return J, float(s[0]), float(s[1])

@@ -34,6 +34,7 @@ __all__ = [
     "adversarial_matrix",
     "tiny_tie_matrix",
     "batched_workload",
+    "rows_to_masks",
 ]
 
 
@@ -329,3 +330,15 @@ def tiny_tie_matrix(rng: np.random.Generator, n_rows: int, n_cols: int,
         for r in range(min(4, n_rows)):
             a[r] = specials[rng.integers(0, len(specials), size=n_cols)]
     return np.ascontiguousarray(a)
+
+
+def rows_to_masks(rows_list: Sequence[Sequence[int]], n_rows: int) -> np.ndarray:
+    """Pack row sets into 64-row words: uint64 [K][W], bit r % 64 of word
+    r // 64 (the layout of the evaluator's row masks)."""
+    W = (n_rows + 63) // 64
+    out = np.zeros((len(rows_list), W), dtype=np.uint64)
+    for k, rows in enumerate(rows_list):
+        r = np.asarray(rows, dtype=np.int64)
+        if r.size:
+            np.bitwise_or.at(out[k], r // 64, np.left_shift(np.uint64(1), (r % 64).astype(np.uint64)))
+    return out

@@ -1,0 +1,162 @@
+"""GPU: Step 6 row lists (ebic_mask_rows) and the recovery / relevance
+scores (ebic_match_scores) against the oracle, bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import scores as oscores
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[scores] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_03039_amd as e
+    return e
+
+
+def _dev(x):
+    import torch
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.uint64:
+        x = x.view(np.int64)                       # same 64-bit words
+    return torch.from_numpy(x).to("cuda:0")
+
+
+def _random_masks(rng, K, planes, n, garbage_tail=True):
+    W = (n + 63) // 64
+    m = rng.integers(0, 2**63, size=(K, planes, W), dtype=np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=(K, planes, W), dtype=np.uint64)
+    if K:
+        m[0] = 0                                   # an empty bicluster
+    if not garbage_tail and n % 64:
+        m[..., -1] &= np.uint64((1 << (n % 64)) - 1)
+    return m
+
+
+@pytest.mark.parametrize("n,K,planes", [(1, 3, 1), (64, 5, 2), (65, 9, 1), (1000, 40, 2),
+                                        (20000, 300, 2), (50000, 3, 1)])
+def test_mask_rows_match_oracle(E, n, K, planes):
+    rng = np.random.default_rng(n + K)
+    masks = _random_masks(rng, K, planes, n)       # bits beyond n must be ignored
+    _note(f"mask_rows n={n} K={K} planes={planes}")
+    off, rows = E.mask_rows(_dev(masks), n)
+    off, rows = off.cpu().numpy(), rows.cpu().numpy()
+    want = oscores.mask_rows(masks, n) if n * K <= 200000 else None
+    if want is None:                               # large: every 7th bicluster by the oracle
+        idx = range(0, K, 7)
+        want_sub = oscores.mask_rows(masks[list(idx)], n)
+        for j, k in enumerate(idx):
+            assert np.array_equal(rows[off[k]:off[k + 1]], want_sub[j])
+        union = np.bitwise_or.reduce(masks, axis=1)
+        if n % 64:
+            union[:, -1] &= np.uint64((1 << (n % 64)) - 1)
+        counts = np.unpackbits(union.view(np.uint8), axis=1).sum(axis=1)
+        assert np.array_equal(np.diff(off), counts)
+    else:
+        assert off[0] == 0
+        assert np.array_equal(np.diff(off), [len(w) for w in want])
+        assert np.array_equal(rows, np.concatenate(want) if want else np.zeros(0, np.int32))
+
+
+def test_mask_rows_of_evaluator_masks(E):
+    w = synth.WORKLOADS["tiny"]
+    a, planted = synth.make_matrix(w)
+    rng = np.random.default_rng(5)
+    pop = synth.mixed_population(rng, w, planted, 64)
+    off, cols = synth.pack_cbf(pop)
+    with E.Context(a) as ctx:
+        _note("evaluate tiny with masks")
+        r = ctx.evaluate(off, cols, sigma=w.sigma, max_violations=1, negative_trends=True,
+                         want_masks=True)
+    masks = r["masks"] if isinstance(r, dict) else r.masks
+    ref = oracle.evaluate(a, off, cols, sigma=w.sigma, max_violations=1, negative_trends=True,
+                          want_masks=True)
+    d_off, d_rows = E.mask_rows(_dev(np.asarray(masks)), w.n_rows)
+    d_off, d_rows = d_off.cpu().numpy(), d_rows.cpu().numpy()
+    want = oscores.mask_rows(ref["masks"], w.n_rows)
+    assert np.array_equal(np.diff(d_off), ref["counts"])          # Step 6 lists hold |I| rows
+    for k in range(len(pop)):
+        assert np.array_equal(d_rows[d_off[k]:d_off[k + 1]], want[k])
+
+
+def test_mask_rows_capacity_and_empty(E):
+    import torch
+    rng = np.random.default_rng(6)
+    n, K = 300, 6
+    masks = _random_masks(rng, K, 2, n)
+    full_off, full_rows = E.mask_rows(_dev(masks), n)
+    cap = int(full_off[-1].item()) // 2
+    off, rows = E.mask_rows(_dev(masks), n, capacity=cap)
+    assert torch.equal(off, full_off)
+    assert torch.equal(rows, full_rows[:cap])
+    off0, rows0 = E.mask_rows(_dev(np.zeros((0, 2, 5), np.uint64)), n=300)
+    assert off0.cpu().tolist() == [0] and rows0.numel() == 0
+    offz, rowsz = E.mask_rows(_dev(np.zeros((4, 0), np.uint64)), 0)
+    assert offz.cpu().tolist() == [0] * 5 and rowsz.numel() == 0
+
+
+def _bicluster_sets(rng, n, m, count, planes=1):
+    rows = [np.sort(rng.choice(n, size=int(rng.integers(0, max(2, n // 3))), replace=False))
+            for _ in range(count)]
+    cols = []
+    for _ in range(count):
+        c = rng.choice(m, size=int(rng.integers(1, min(m, 40) + 1)), replace=False)
+        if rng.random() < 0.2:
+            c = np.concatenate([c, c[:2]])          # repeated columns count once
+        cols.append(c.astype(np.int32))
+    masks = synth.rows_to_masks(rows, n)
+    if planes == 2:                                  # split each row set over two planes
+        split = masks & rng.integers(0, 2**63, size=masks.shape, dtype=np.uint64)
+        masks = np.stack([split, masks & ~split], axis=1)
+    c_off, c_cols = synth.pack_cbf([list(c) for c in cols]) if count else (np.zeros(1, np.int32), np.zeros(0, np.int32))
+    return rows, cols, (masks, c_off, c_cols)
+
+
+@pytest.mark.parametrize("n,m,F,Ecount", [(10, 6, 5, 3), (200, 50, 37, 10), (5000, 1000, 100, 20),
+                                          (777, 30, 1, 1), (100, 10, 0, 4), (100, 10, 4, 0)])
+def test_match_scores_match_oracle(E, n, m, F, Ecount):
+    rng = np.random.default_rng(n + F)
+    fr, fc, fset = _bicluster_sets(rng, n, m, F, planes=2)
+    er, ec, eset = _bicluster_sets(rng, n, m, Ecount)
+    _note(f"match_scores n={n} F={F} E={Ecount}")
+    J, rec, rel = E.match_scores(tuple(_dev(x) for x in fset), tuple(_dev(x) for x in eset), n)
+    Jr, rec_r, rel_r = oscores.match_scores(list(zip(fr, fc)), list(zip(er, ec)))
+    assert np.array_equal(J.cpu().numpy().view(np.int64), Jr.view(np.int64))
+    assert np.float64(rec).view(np.int64) == np.float64(rec_r).view(np.int64)
+    assert np.float64(rel).view(np.int64) == np.float64(rel_r).view(np.int64)
+
+
+def test_recovery_of_planted_biclusters(E):
+    # the planted truth against itself, and against the biclusters an
+    # evaluation of the planted series finds (same columns, matched rows)
+    w = synth.WORKLOADS["tiny"]
+    a, planted = synth.make_matrix(w)
+    n = w.n_rows
+    truth_rows = [p.rows for p in planted]
+    truth_cols = [list(p.cols) for p in planted]
+    t_off, t_cols = synth.pack_cbf(truth_cols)
+    tset = (_dev(synth.rows_to_masks(truth_rows, n)), _dev(t_off), _dev(t_cols))
+    J, rec, rel = E.match_scores(tset, tset, n)
+    assert rec == 1.0 and rel == 1.0
+    with E.Context(a) as ctx:
+        r = ctx.evaluate(t_off, t_cols, sigma=w.sigma, want_masks=True)
+    masks = np.asarray(r["masks"] if isinstance(r, dict) else r.masks)
+    fset = (_dev(masks), _dev(t_off), _dev(t_cols))
+    J, rec, rel = E.match_scores(fset, tset, n)
+    found_rows = oscores.mask_rows(masks, n)
+    Jr, rec_r, rel_r = oscores.match_scores(list(zip(found_rows, truth_cols)),
+                                            list(zip(truth_rows, truth_cols)))
+    assert (rec, rel) == (rec_r, rel_r)
+    assert rec > 0.5
