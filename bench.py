@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-direct", action="store_true", help="skip timing the direct path")
     ap.add_argument("--evolve-gens", type=int, default=-1, help="generations (-1: workload's)")
+    ap.add_argument("--surrogate-seeds", type=int, default=3,
+                    help="seeds of the plain-vs-surrogate comparison (--workload surrogate)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (a kernel of "
                          "known traffic, to calibrate rocprof FETCH_SIZE/WRITE_SIZE)")
@@ -240,8 +242,110 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def recovery_vs_planted(ebic, res, planted, n_rows, dev):
+    """Recovery and relevance (Eqs. 2-3) of a run's top list against the
+    planted biclusters, on the device."""
+    import torch
+    import synth
+    if not res.biclusters:
+        return 0.0, 0.0
+    f_masks = np.stack([b["mask_words"] for b in res.biclusters]).view(np.int64)
+    f_off, f_cols = synth.pack_cbf([list(b["cols"]) for b in res.biclusters])
+    t_masks = synth.rows_to_masks([p.rows for p in planted], n_rows).view(np.int64)
+    t_off, t_cols = synth.pack_cbf([list(p.cols) for p in planted])
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    _, rec, rel = ebic.match_scores((d(f_masks), d(f_off), d(f_cols)),
+                                    (d(t_masks), d(t_off), d(t_cols)), n_rows)
+    return rec, rel
+
+
+def run_surrogate(args):
+    """Plain EBIC against the surrogate-screened run on the same matrix and
+    seeds: wall time until each run first holds a candidate of fitness >= F*
+    (F* = the plain run's best), and recovery of the final top lists."""
+    import torch
+    import synth
+    import paper_1801_03039_amd as ebic
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["surrogate"]
+    G = w.generations if args.evolve_gens < 0 else args.evolve_gens
+    a, planted = synth.make_matrix(w)
+    ctx = ebic.Context(torch.from_numpy(a).to(dev))
+    cfg = ebic.EvolveConfig(population=w.population, len_min=w.len_min, len_max=w.len_max,
+                            eval=ebic.Trend(w.sigma, w.max_violations, w.negative_trends),
+                            expand=ebic.Trend(w.sigma, w.max_violations, True),
+                            overlap=w.overlap, toplist_size=w.toplist, tournament=w.tournament)
+
+    def timed(fn, **kw):
+        trace = []
+        t0 = time.perf_counter()
+
+        def on_gen(g):
+            trace.append((time.perf_counter() - t0, float(g.fitness.max(initial=0.0))))
+        res = fn(on_generation=on_gen, **kw)
+        return res, trace, time.perf_counter() - t0
+
+    def first_reach(trace, target):
+        best = 0.0
+        for t, f in trace:
+            best = max(best, f)
+            if best >= target:
+                return t
+        return None
+
+    seeds = [w.seed + 100 + i for i in range(args.surrogate_seeds)]
+    runs = []
+    for seed in seeds:
+        log(f"surrogate bench: plain run seed {seed}")
+        rp, tp, wp = timed(lambda **kw: ebic.evolve(ctx, seed, G, cfg, **kw))
+        log(f"surrogate bench: screened run seed {seed}")
+        info = []
+        rs, ts, ws_ = timed(lambda **kw: ebic.evolve_surrogate(ctx, seed, G, cfg,
+                                                               on_surrogate=info.append, **kw))
+        f_star = max(f for _, f in tp)
+        t_plain, t_sur = first_reach(tp, f_star), first_reach(ts, f_star)
+        rec_p, rel_p = recovery_vs_planted(ebic, rp, planted, w.n_rows, dev)
+        rec_s, rel_s = recovery_vs_planted(ebic, rs, planted, w.n_rows, dev)
+        runs.append({
+            "seed": seed, "f_star": f_star,
+            "plain": {"t_f_star_s": round(t_plain, 4), "wall_s": round(wp, 3),
+                      "generations": len(tp), "recovery": round(rec_p, 4),
+                      "relevance": round(rel_p, 4)},
+            "surrogate": {"t_f_star_s": None if t_sur is None else round(t_sur, 4),
+                          "best": max(f for _, f in ts), "wall_s": round(ws_, 3),
+                          "generations": len(ts), "recovery": round(rec_s, 4),
+                          "relevance": round(rel_s, 4),
+                          "screened_generations": sum(1 for i in info if i["screened"]),
+                          "mean_rank_corr": round(float(np.mean([i["rank_corr"] for i in info
+                                                                 if i["gen"] > 1] or [0])), 4)},
+            "speedup_at_f_star": None if t_sur is None else round(t_plain / t_sur, 3),
+        })
+        log(json.dumps(runs[-1]))
+    ctx.close()
+    sp = [r["speedup_at_f_star"] for r in runs]
+    out = {
+        "metric": "surrogate speedup at equal fitness",
+        "value": None if any(x is None for x in sp) else round(float(np.exp(np.mean(np.log(sp)))), 3),
+        "unit": "x (geometric mean of T_plain(F*) / T_surrogate(F*))",
+        "n_gpus": 1, "steps": len(seeds), "warmup": 0, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 eval, bf16 MLP", "data": "synthetic",
+        "config": {"workload": f"surrogate: {w.n_rows}x{w.n_cols} {w.background}, "
+                               f"{w.n_planted} planted, P={w.population}, L {w.len_min}-{w.len_max}, "
+                               f"k={w.max_violations}, rising+falling, sigma={w.sigma}, G={G}",
+                   "seeds": seeds},
+        "runs": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "surrogate":
+        if args.gpus != 1:
+            print(json.dumps({"error": "one GPU only", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return run_surrogate(args)
     if args.workload == "batched":
         if args.gpus != 1:
             print(json.dumps({"error": "one GPU only", "n_gpus": args.gpus}))
