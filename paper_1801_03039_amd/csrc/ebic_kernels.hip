@@ -295,6 +295,7 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 // every enabled direction.
 constexpr int kIdxLds = 4096;   // staged column entries per workgroup
 constexpr int kUnroll = 4;   // pairs per batch of loads (single-run default)
+constexpr int kWordsPerLane = 1;   // 64-row words per lane (single-run kernel)
 
 template <int K, bool NEG>
 __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1], uint64_t lt_pq,
@@ -311,9 +312,28 @@ __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1
     }
 }
 
-// One tile (kBlock consecutive items) of one run.  Shared by the single-run
-// kernel (tile = workgroup) and the persistent multi-run kernel.
-template <int K, bool NEG, int U>
+// V consecutive order words of one pair, read with 16-byte loads when V > 1
+// (the caller keeps the address 16-byte aligned).
+template <int V>
+__device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = p[0];
+    } else {
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            const u64x2 x = *(global_ptr<u64x2>)(p + i);
+            o[i] = x.x;
+            o[i + 1] = x.y;
+        }
+    }
+}
+
+// One tile (kBlock consecutive items) of one run.  An item is a candidate
+// and V consecutive 64-row words of it (V words per lane share the lane's
+// column reads and loop).  Shared by the single-run kernel (tile =
+// workgroup) and the persistent multi-run kernel.
+template <int K, bool NEG, int U, int V>
 __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
                                            const int32_t *__restrict__ offsets,
                                            const int32_t *__restrict__ cols, int64_t n_entries,
@@ -321,6 +341,7 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
                                            unsigned long long *__restrict__ acc,
                                            int32_t *__restrict__ counts,
                                            double *__restrict__ fitness) {
+    static_assert(V == 1 || V == 2 || V == 4, "words per lane");
     __shared__ int32_t s_cols[kIdxLds];
     const auto idx = as_global(R.idx);
     const auto tie = as_global(R.tie);
@@ -328,13 +349,14 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     const int64_t n = R.n, W = R.W, wpad = R.wpad;
     const int32_t m = R.m, P = R.P;
     const int tid = threadIdx.x, lane = tid & 63;
-    // The launcher guarantees P * W < 2^32.
-    const uint32_t Wu = (uint32_t)W;
+    // The launcher guarantees P * ceil(W / V) < 2^32.
+    const uint32_t Wg = (uint32_t)((W + V - 1) / V);   // items per candidate
     const uint32_t item = tile * (uint32_t)kBlock + (uint32_t)tid;
-    const uint32_t total = (uint32_t)P * Wu;
+    const uint32_t total = (uint32_t)P * Wg;
     const bool active = item < total;
-    const uint32_t cl = active ? item / Wu : (uint32_t)P - 1;   // candidate within the run
-    const uint32_t w = active ? item - cl * Wu : 0;
+    const uint32_t cl = active ? item / Wg : (uint32_t)P - 1;   // candidate within the run
+    const uint32_t g = active ? item - cl * Wg : 0;
+    const int64_t w0 = (int64_t)g * V;                           // first word of the item
     const int64_t c = R.cand_base + cl;                          // candidate in the launch
 
     const int64_t start = offsets[c], end = offsets[c + 1];
@@ -346,8 +368,8 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     // well-formed CBF); otherwise the whole workgroup reads them from global
     // memory.  The choice is uniform over the workgroup.
     const uint32_t i0 = tile * (uint32_t)kBlock;
-    const uint32_t c_lo = i0 / Wu;
-    const uint32_t c_hi = min((i0 + kBlock - 1) / Wu, (uint32_t)P - 1);
+    const uint32_t c_lo = i0 / Wg;
+    const uint32_t c_hi = min((i0 + kBlock - 1) / Wg, (uint32_t)P - 1);
     const int64_t b0 = offsets[R.cand_base + c_lo], b1 = offsets[R.cand_base + c_hi + 1];
     const bool span_ok = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
     const bool lane_ok = !ok_range || (start >= b0 && end <= b1);
@@ -358,10 +380,18 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     }
     const int32_t lds0 = (int32_t)(start - b0);
 
-    const uint64_t valid = (active && ok_range) ? tail_bits(n, w, W) : 0ull;
-    uint64_t cu[K + 1], cd[K + 1];
+    uint64_t valid[V];
+    uint64_t any_valid = 0;
 #pragma unroll
-    for (int i = 0; i <= K; ++i) cu[i] = cd[i] = 0ull;
+    for (int v = 0; v < V; ++v) {
+        valid[v] = (active && ok_range && w0 + v < W) ? tail_bits(n, w0 + v, W) : 0ull;
+        any_valid |= valid[v];
+    }
+    uint64_t cu[V][K + 1], cd[V][K + 1];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int i = 0; i <= K; ++i) cu[v][i] = cd[v][i] = 0ull;
     bool bad = false;
 
     // Per-lane work, instantiated for columns in LDS or in global memory.
@@ -371,48 +401,49 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
             if constexpr (kLds) return s_cols[lds0 + t];
             else return cols[start + t];
         };
-        // The lane of word 0 validates every column (batched, branch-free
-        // reads) and reports the verdict with its part; other lanes only
-        // clamp column indices so that no read leaves the index.
-        if (active && w == 0) {
+        // The lane of the first word validates every column (batched,
+        // branch-free reads) and reports the verdict with its part; other
+        // lanes only clamp column indices so that no read leaves the index.
+        if (active && g == 0) {
             bad = !ok_range;
             for (int32_t t = 0; t < L; t += U) {
-                int32_t v[U];
+                int32_t x[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) v[u] = col(min(t + u, L - 1));
+                for (int u = 0; u < U; ++u) x[u] = col(min(t + u, L - 1));
 #pragma unroll
-                for (int u = 0; u < U; ++u) bad |= (v[u] < 0 || v[u] >= m);
+                for (int u = 0; u < U; ++u) bad |= (x[u] < 0 || x[u] >= m);
             }
         }
-        if (!valid) return;
-        const auto base = idx + w;
+        if (!any_valid) return;
+        const auto base = idx + w0;
         const int32_t last = L - 1;
         int32_t p = col(0);
         p = (p < 0 || p >= m) ? 0 : p;
         for (int32_t t = 1; t < L; t += U) {
             // Column reads and order-word loads of the batch are issued
             // unconditionally (indices past the end repeat the last column,
-            // a harmless in-bounds read whose word is then ignored).
+            // a harmless in-bounds read whose words are then ignored).
             int32_t q[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int32_t v = col(min(t + u, last));
-                q[u] = (v < 0 || v >= m) ? 0 : v;
+                const int32_t x = col(min(t + u, last));
+                q[u] = (x < 0 || x >= m) ? 0 : x;
             }
-            uint64_t lu[U], ld[U];
+            uint64_t lu[U][V], ld[U][V];
             uint8_t tf[U];
             int32_t pp = p;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t pq = (int64_t)pp * m + q[u];
-                lu[u] = base[pq * wpad];
+                load_words<V>(base + pq * wpad, lu[u]);
                 if (NEG) tf[u] = tie[pq];
                 pp = q[u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool in = t + u < L;
-                lu[u] = in ? lu[u] : ~0ull;
+#pragma unroll
+                for (int v = 0; v < V; ++v) lu[u][v] = in ? lu[u][v] : ~0ull;
                 if (NEG) tf[u] = in ? tf[u] : 0;
             }
             if (NEG) {
@@ -421,16 +452,28 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
                 pp = p;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint64_t rev = tf[u] ? base[((int64_t)q[u] * m + pp) * wpad] : ~lu[u];
-                    ld[u] = t + u < L ? rev : ~0ull;
+                    if (tf[u]) {
+                        load_words<V>(base + ((int64_t)q[u] * m + pp) * wpad, ld[u]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
+                    }
+#pragma unroll
+                    for (int v = 0; v < V; ++v) ld[u][v] = t + u < L ? ld[u][v] : ~0ull;
                     pp = q[u];
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) fold<K, NEG>(cu, cd, lu[u], NEG ? ld[u] : 0ull);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    fold<K, NEG>(cu[v], cd[v], lu[u][v], NEG ? ld[u][v] : 0ull);
             p = pp;
-            const uint64_t dead = NEG ? (cu[K] & cd[K]) : cu[K];
-            if ((valid & ~dead) == 0ull) break;
+            uint64_t live = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                live |= valid[v] & ~(NEG ? (cu[v][K] & cd[v][K]) : cu[v][K]);
+            if (live == 0ull) break;
         }
     };
     if (use_lds)
@@ -438,41 +481,48 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     else
         lane_work(std::false_type{});
 
-    const uint64_t pos = valid & ~cu[K];
-    const uint64_t neg = NEG ? (valid & ~cd[K]) : 0ull;
-    if (masks && active) {
-        masks[R.mask_base + ((int64_t)cl * 2 + 0) * W + w] = pos;
-        masks[R.mask_base + ((int64_t)cl * 2 + 1) * W + w] = neg;
+    int32_t rows = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const uint64_t pos = valid[v] & ~cu[v][K];
+        const uint64_t neg = NEG ? (valid[v] & ~cd[v][K]) : 0ull;
+        rows += __popcll(pos | neg);
+        if (masks && active && w0 + v < W) {
+            masks[R.mask_base + ((int64_t)cl * 2 + 0) * W + w0 + v] = pos;
+            masks[R.mask_base + ((int64_t)cl * 2 + 1) * W + w0 + v] = neg;
+        }
     }
 
     // Segmented sum over lanes of the same candidate (lanes hold consecutive
     // items, so each candidate is one contiguous run of lanes): the run's
-    // head gets the run's row count (low 16 bits, <= 64*64) and its number
+    // head gets the run's row count (low 16 bits, <= 64*64*V) and its number
     // of words (high bits), then reports them once.
-    int32_t packed = active ? (__popcll(pos | neg) | (1 << 16)) : 0;
+    const int32_t words = active ? (int32_t)min<int64_t>(V, W - w0) : 0;
+    int32_t packed = active ? (rows | (words << 16)) : 0;
     const int32_t cc = (int32_t)cl;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const int32_t v = __shfl_down(packed, off);
+        const int32_t x = __shfl_down(packed, off);
         const int32_t oc = __shfl_down(cc, off);
-        if (lane + off < kWave && oc == cc) packed += v;
+        if (lane + off < kWave && oc == cc) packed += x;
     }
     const int32_t prev_c = __shfl_up(cc, 1);
     const bool head = lane == 0 || prev_c != cc;
-    // word 0 is always the first lane of its run, hence a head itself.
+    // the first item of a candidate is always the first lane of its run,
+    // hence a head itself.
     if (active && head)
         finish_part(c, (uint32_t)(packed & 0xFFFF), bad, packed >> 16, W, L, sigma, logt, acc,
                     counts, fitness);
 }
 
-template <int K, bool NEG, int U>
+template <int K, bool NEG, int U, int V>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     IndexRun R, const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols,
     int64_t n_entries, int32_t sigma, uint64_t *__restrict__ masks,
     unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
     double *__restrict__ fitness) {
-    index_tile<K, NEG, U>(R, blockIdx.x, offsets, cols, n_entries, sigma, masks, acc, counts,
-                          fitness);
+    index_tile<K, NEG, U, V>(R, blockIdx.x, offsets, cols, n_entries, sigma, masks, acc, counts,
+                             fitness);
 }
 
 // --------------------------------------------------- batched (many runs) --
@@ -515,8 +565,8 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
         const uint32_t t = s_tile;
         if (t >= total_tiles) break;  // uniform
         const int32_t r = s_run;
-        index_tile<K, NEG, U>(runs[r], t - tile_base[r], offsets, cols, n_entries, sigma, masks,
-                              acc, counts, fitness);
+        index_tile<K, NEG, U, 1>(runs[r], t - tile_base[r], offsets, cols, n_entries, sigma,
+                                 masks, acc, counts, fitness);
     }
     if (threadIdx.x == 0) {
         const unsigned left = atomicAdd(work + 1, 1u);
@@ -581,14 +631,15 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
 
 template <int K, int U>
 static void launch_index_k(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
-    const int64_t total = (int64_t)R.P * R.W;
+    constexpr int V = kWordsPerLane;
+    const int64_t total = (int64_t)R.P * ((R.W + V - 1) / V);
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
     if (e.negative)
-        hipLaunchKernelGGL((eval_index_kernel<K, true, U>), grid, dim3(kBlock), 0, stream, R,
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V>), grid, dim3(kBlock), 0, stream, R,
                            e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
                            e.fitness);
     else
-        hipLaunchKernelGGL((eval_index_kernel<K, false, U>), grid, dim3(kBlock), 0, stream, R,
+        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V>), grid, dim3(kBlock), 0, stream, R,
                            e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
                            e.fitness);
 }

@@ -10,7 +10,6 @@
 #include <cstring>
 #include <new>
 #include <string>
-#include <unordered_set>
 #include <vector>
 
 #include "../../include/ebic.h"
@@ -77,55 +76,68 @@ struct Pop {
 // an append-only arena; the set holds (offset, length) keys into it.
 class Tabu {
   public:
-    Tabu() : set_(1024, Hash{&arena_}, Eq{&arena_}) {}
-    bool contains(const int32_t *s, int32_t L) {
-        const size_t at = stage(s, L);
-        const bool hit = set_.find(Key{at, L}) != set_.end();
-        arena_.resize(at);
-        return hit;
+    Tabu() : slots_(1024) {}
+    bool contains(const int32_t *s, int32_t L) const {
+        const uint64_t h = hash(s, L);
+        return slots_[find(s, L, h)].len >= 0;
     }
     // Inserts; returns false when already present.
     bool insert(const int32_t *s, int32_t L) {
-        const size_t at = stage(s, L);
-        if (!set_.insert(Key{at, L}).second) {
-            arena_.resize(at);
-            return false;
+        const uint64_t h = hash(s, L);
+        size_t i = find(s, L, h);
+        if (slots_[i].len >= 0) return false;
+        if (2 * (used_ + 1) > slots_.size()) {
+            grow();
+            i = find(s, L, h);
         }
+        slots_[i] = Slot{h, arena_.size(), L};
+        arena_.insert(arena_.end(), s, s + L);
+        ++used_;
         return true;
     }
 
   private:
-    struct Key {
-        size_t at;
-        int32_t len;
+    // Open addressing with linear probing over a power-of-two table kept at
+    // most half full; series live in one arena.
+    struct Slot {
+        uint64_t h = 0;
+        size_t at = 0;
+        int32_t len = -1;   // -1: empty
     };
-    struct Hash {
-        const std::vector<int32_t> *a;
-        size_t operator()(const Key &k) const {
-            uint64_t h = 0x84222325cbf29ce4ull ^ (uint64_t)k.len;
-            const int32_t *p = a->data() + k.at;
-            for (int32_t i = 0; i < k.len; ++i) {
-                h ^= (uint32_t)p[i];
-                h *= 0x100000001b3ull;
-                h ^= h >> 29;
-            }
-            return (size_t)h;
+    static uint64_t hash(const int32_t *p, int32_t L) {
+        uint64_t h = 0x84222325cbf29ce4ull ^ (uint64_t)L;
+        for (int32_t i = 0; i < L; ++i) {
+            h ^= (uint32_t)p[i];
+            h *= 0x100000001b3ull;
+            h ^= h >> 29;
         }
-    };
-    struct Eq {
-        const std::vector<int32_t> *a;
-        bool operator()(const Key &x, const Key &y) const {
-            return x.len == y.len &&
-                   std::memcmp(a->data() + x.at, a->data() + y.at, sizeof(int32_t) * x.len) == 0;
+        return h ^ (h >> 32);
+    }
+    // Slot holding the series, or the empty slot where it would go.
+    size_t find(const int32_t *s, int32_t L, uint64_t h) const {
+        const size_t mask = slots_.size() - 1;
+        for (size_t i = (size_t)h & mask;; i = (i + 1) & mask) {
+            const Slot &e = slots_[i];
+            if (e.len < 0) return i;
+            if (e.h == h && e.len == L &&
+                std::memcmp(arena_.data() + e.at, s, sizeof(int32_t) * (size_t)L) == 0)
+                return i;
         }
-    };
-    size_t stage(const int32_t *s, int32_t L) {
-        const size_t at = arena_.size();
-        arena_.insert(arena_.end(), s, s + L);
-        return at;
+    }
+    void grow() {
+        std::vector<Slot> old((size_t)2 * slots_.size());
+        old.swap(slots_);
+        const size_t mask = slots_.size() - 1;
+        for (const Slot &e : old) {
+            if (e.len < 0) continue;
+            size_t i = (size_t)e.h & mask;
+            while (slots_[i].len >= 0) i = (i + 1) & mask;
+            slots_[i] = e;
+        }
     }
     std::vector<int32_t> arena_;
-    std::unordered_set<Key, Hash, Eq> set_;
+    std::vector<Slot> slots_;
+    size_t used_ = 0;
 };
 
 struct TopEntry {
@@ -427,14 +439,25 @@ class Run {
             const int32_t L = prev_.len(i);
             int64_t sum = 0;
             for (int32_t t = 0; t < L; ++t) sum += penalty_[(size_t)si[t]];
-            const double vartheta = (double)sum / (double)L;
-            const double adj = prev_.fit[(size_t)i] / std::pow(p_.penalty_base, vartheta);
+            const double adj = prev_.fit[(size_t)i] / penalty_pow(sum, L);
             if (adj > best_adj) {
                 best = i;
                 best_adj = adj;
             }
         }
         return best;
+    }
+
+    // base^(sum / L), the crowding penalty of a series of length L whose
+    // columns hold `sum` penalty points, memoised per (L, sum): the value is
+    // the same double std::pow returns for those arguments.
+    double penalty_pow(int64_t sum, int32_t L) {
+        if ((size_t)L >= pow_memo_.size()) pow_memo_.resize((size_t)L + 1);
+        std::vector<double> &t = pow_memo_[(size_t)L];
+        if ((size_t)sum >= t.size()) t.resize(std::max<size_t>((size_t)sum + 1, 2 * t.size()), -1.0);
+        double &v = t[(size_t)sum];
+        if (!(v >= 0.0)) v = std::pow(p_.penalty_base, (double)sum / (double)L);
+        return v;
     }
 
     // Step 2: elites from the top-rank list, penalties of their columns.
@@ -554,6 +577,7 @@ class Run {
     Tabu tabu_;
     TopRank toprank_;
     std::vector<int32_t> penalty_, s_, child_;
+    std::vector<std::vector<double>> pow_memo_;
     Pop prev_, cur_, pool_;
     ebic_params evalp_{};
     int64_t wsum_ = 0;
