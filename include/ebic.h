@@ -256,6 +256,24 @@ ebic_status ebic_evolve_with(ebic_eval_fn eval, void *eval_user, int64_t n_rows,
                              uint64_t seed, int32_t generations,
                              const ebic_evolve_params *params, ebic_result **out);
 
+/*
+ * Offspring screening with a caller-supplied ranking (not in the paper; the
+ * host side of ebic_evolve_surrogate with any scorer, e.g. exact fitness).
+ * Generations after warmup_generations draw a pool of oversample x (P -
+ * elites) novel children and keep the P - elites that score ranks highest;
+ * see ebic_evolve_surrogate for the pool rules.  score receives the pool as
+ * host CBF (B series) and fills scores[B] (higher is better; NaN ranks last)
+ * and returns EBIC_OK.  host_threads (<= 0: the hardware's) draws the pool in
+ * parallel; results do not depend on it.  eval as in ebic_evolve_with.
+ */
+typedef ebic_status (*ebic_score_fn)(void *user, const int32_t *offsets, const int32_t *cols,
+                                     int32_t B, float *scores);
+ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_user, ebic_score_fn score,
+                                      void *score_user, int64_t n_rows, int32_t n_cols,
+                                      uint64_t seed, int32_t generations, int32_t oversample,
+                                      int32_t warmup_generations, int32_t host_threads,
+                                      const ebic_evolve_params *params, ebic_result **out);
+
 /* Result of a run: the top-rank biclusters after Step 7, best first. */
 typedef struct {
     uint32_t struct_size;       /* sizeof(ebic_run_stats) */
@@ -386,7 +404,13 @@ ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32
  * Surrogate-screened run (not in the paper).  As ebic_evolve, except that
  * after `warmup_generations` a generation draws oversample x (P - elites)
  * novel children and keeps the P - elites that the surrogate MLP ranks
- * highest (see ebic_evolve's Step 3 readings for how children are drawn).
+ * highest.  The pool is drawn by 16 breeders in parallel: breeder j draws an
+ * equal share by Step 3's rules (tournament with crowding penalties starting
+ * from the elites' and adding its own children's, one operation, novel with
+ * respect to the tabu list and its share) from a stream seeded by the j-th
+ * of 16 draws of the run's stream; shares are joined in order without
+ * repeats (the run's own breeder tops up a short pool).  The outcome does not
+ * depend on the number of host threads.
  * Every kept child is scored exactly on the GPU; only kept children enter
  * the tabu list.  The model is trained each generation (train_steps Adam
  * steps) on the exact (candidate, log(1 + fitness)) pairs of the last

@@ -440,6 +440,67 @@ def evolve_with(evaluate: Callable, n_rows: int, n_cols: int, seed: int, generat
     return _finish(res, n_rows)
 
 
+SCORE_FN = ctypes.CFUNCTYPE(_i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32,
+                            ctypes.POINTER(ctypes.c_float))
+_evolve_screened_with = _sig("ebic_evolve_screened_with", _i32,
+                             [EVAL_FN, _vp, SCORE_FN, _vp, _i64, _i32, _u64, _i32, _i32, _i32, _i32,
+                              _P(EvolveParamsC), _P(_vp)])
+EXPORTED += ["ebic_evolve_screened_with"]
+
+
+def evolve_screened_with(evaluate: Callable, score: Callable, n_rows: int, n_cols: int, seed: int,
+                         generations: int, cfg: EvolveConfig, oversample: int = 8,
+                         warmup_generations: int = 3, host_threads: int = 0,
+                         on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
+    """Offspring-screened run with caller-supplied evaluator and ranking
+    (``ebic_evolve_screened_with``).  ``evaluate`` as in ``evolve_with``;
+    ``score(offsets, cols)`` returns one float per pooled child (higher is
+    better)."""
+    W = mask_words(n_rows)
+    errors = []
+
+    def ecb(user, off, cols, P, prm, masks, counts, fit):
+        try:
+            o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
+            n = int(o[-1])
+            c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+            pr = prm.contents
+            cnt, f, m = evaluate(o, c, pr.sigma, pr.max_violations, bool(pr.negative_trends),
+                                 bool(pr.want_masks))
+            np.ctypeslib.as_array(counts, shape=(P,))[:] = cnt
+            np.ctypeslib.as_array(fit, shape=(P,))[:] = f
+            if pr.want_masks:
+                np.ctypeslib.as_array(masks, shape=(P * 2 * W,))[:] = np.asarray(m, dtype=np.uint64).ravel()
+            return EBIC_OK
+        except Exception as ex:  # reported after the run
+            errors.append(ex)
+            return EBIC_E_DEVICE
+
+    def scb(user, off, cols, B, out):
+        try:
+            o = np.ctypeslib.as_array(off, shape=(B + 1,)).copy()
+            n = int(o[-1])
+            c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+            np.ctypeslib.as_array(out, shape=(B,))[:] = np.asarray(score(o, c), dtype=np.float32)
+            return EBIC_OK
+        except Exception as ex:
+            errors.append(ex)
+            return EBIC_E_DEVICE
+
+    efn, sfn = EVAL_FN(ecb), SCORE_FN(scb)
+    gcb = _gen_callback(on_generation)
+    p = _params_c(cfg, gcb)
+    res = _vp()
+    st = _evolve_screened_with(efn, None, sfn, None, int(n_rows), int(n_cols),
+                               int(seed) & ((1 << 64) - 1), int(generations), int(oversample),
+                               int(warmup_generations), int(host_threads), ctypes.byref(p),
+                               ctypes.byref(res))
+    if errors:
+        raise errors[0]
+    _check(st)
+    return _finish(res, n_rows)
+
+
 # -------------------------------------------------------------- batched runs --
 
 class BatchTuning(ctypes.Structure):

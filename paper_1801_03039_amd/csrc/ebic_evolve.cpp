@@ -101,6 +101,64 @@ ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t
     return EBIC_OK;
 }
 
+// Screened run with a caller-supplied scorer (the host side of the
+// surrogate-screened run, with any ranking).  Generations after `warmup`
+// draw an oversampled pool and keep the children `score` ranks highest.
+ebic_status run_screened(Evaluator &ev, ebic_score_fn score, void *score_user, int64_t n_rows,
+                         int32_t M, uint64_t seed, int32_t generations, int32_t oversample,
+                         int32_t warmup, int32_t threads, const ebic_evolve_params &p,
+                         ebic_result **out) {
+    const auto t_start = Clock::now();
+    const int64_t W = (n_rows + 63) / 64;
+    Run run(M, seed, generations, p);
+    std::vector<int32_t> cnt, po;
+    std::vector<double> fit;
+    ebic_status score_st = EBIC_OK;
+    auto scorer = [&](const Pop &pool) {
+        std::vector<float> sc((size_t)pool.size(), -INFINITY);
+        ebic_status e = score(score_user, pool.off.data(), pool.cols.data(), pool.size(), sc.data());
+        if (e != EBIC_OK) score_st = e;
+        return sc;
+    };
+    for (;;) {
+        const bool screen = run.generation() > warmup;
+        const bool more = screen ? run.next_screened(oversample, scorer, threads) : run.next();
+        if (score_st != EBIC_OK) return score_st;
+        if (!more) break;
+        const Pop &pop = run.pending();
+        const int32_t first = run.first_new();
+        cnt.resize((size_t)(pop.size() - first));
+        fit.resize(cnt.size());
+        ebic_status st = ev(pop, first, &run.eval_params(), nullptr, cnt.data(), fit.data());
+        if (st != EBIC_OK) return st;
+        run.accept(cnt.data(), fit.data());
+    }
+    const std::vector<TopEntry> &top = run.top();
+    const int32_t K = (int32_t)top.size();
+    std::vector<uint64_t> masks((size_t)K * 2 * (size_t)W);
+    std::vector<int32_t> rc((size_t)K);
+    std::vector<double> rf((size_t)K);
+    if (K > 0) {
+        Pop tp;
+        for (const TopEntry &e : top) tp.push(e.s.data(), (int32_t)e.s.size());
+        ebic_params ex = p.expand;
+        ex.want_masks = 1;
+        ebic_status st = ev(tp, 0, &ex, masks.data(), rc.data(), rf.data());
+        if (st != EBIC_OK) return st;
+    }
+    ebic_result *r = make_result(top, W, masks, std::move(rc), std::move(rf));
+    if (!r) return evolve_error(EBIC_E_NOMEM, "cannot allocate result");
+    r->stats.struct_size = sizeof(ebic_run_stats);
+    r->stats.generations_run = run.generations_run();
+    r->stats.stopped_by_tabu = run.stopped() ? 1 : 0;
+    r->stats.candidates_evaluated = ev.evaluated;
+    r->stats.wall_ms = ms_since(t_start);
+    r->stats.eval_ms = ev.ms;
+    r->stats.host_ms = r->stats.wall_ms - ev.ms;
+    *out = r;
+    return EBIC_OK;
+}
+
 ebic_status ctx_eval(void *user, const int32_t *offsets, const int32_t *cols, int32_t P,
                      const ebic_params *p, uint64_t *masks, int32_t *counts, double *fitness) {
     return ebic_evaluate(static_cast<ebic_ctx *>(user), offsets, cols, P, p, masks, counts,
@@ -182,3 +240,21 @@ ebic_status ebic_result_stats(const ebic_result *r, ebic_run_stats *stats) {
 void ebic_result_free(ebic_result *r) { delete r; }
 
 }  // extern "C"
+
+extern "C" ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_user,
+                                                 ebic_score_fn score, void *score_user,
+                                                 int64_t n_rows, int32_t n_cols, uint64_t seed,
+                                                 int32_t generations, int32_t oversample,
+                                                 int32_t warmup_generations, int32_t host_threads,
+                                                 const ebic_evolve_params *params,
+                                                 ebic_result **out) {
+    if (!eval || !score || !out) return evolve_error(EBIC_E_ARG, "eval, score and out must not be null");
+    if (generations < 0 || oversample < 1 || warmup_generations < 0)
+        return evolve_error(EBIC_E_ARG, "need generations >= 0, oversample >= 1, warmup >= 0");
+    ebic_status st = check_params(params, n_rows, n_cols);
+    if (st != EBIC_OK) return st;
+    *out = nullptr;
+    Evaluator ev{eval, eval_user};
+    return run_screened(ev, score, score_user, n_rows, n_cols, seed, generations, oversample,
+                        warmup_generations, host_threads, *params, out);
+}

@@ -6,10 +6,12 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ebic.h"
@@ -361,6 +363,82 @@ inline ebic_status check_params(const ebic_evolve_params *p, int64_t n_rows, int
     return EBIC_OK;
 }
 
+// Step 3 draws: tournament selection with the crowding penalty, then one
+// genetic operation.  Holds its own random stream, penalty counts and child
+// buffer, so that several can draw in parallel from one population.
+class Breeder {
+  public:
+    Breeder(const ebic_evolve_params &p, int32_t M, uint64_t seed)
+        : p_(&p), M_(M), rng(seed), penalty((size_t)M) {
+        for (int i = 0; i < 5; ++i) wsum_ += p.op_weight[i];
+    }
+
+    // Tournament over `prev` with the crowding penalty.
+    int32_t tournament(const Pop &prev) {
+        int32_t best = -1;
+        double best_adj = -INFINITY;
+        for (int32_t r = 0; r < p_->tournament; ++r) {
+            const int32_t i = (int32_t)rng.below((uint64_t)prev.size());
+            const int32_t *si = prev.series(i);
+            const int32_t L = prev.len(i);
+            int64_t sum = 0;
+            for (int32_t t = 0; t < L; ++t) sum += penalty[(size_t)si[t]];
+            const double adj = prev.fit[(size_t)i] / penalty_pow(sum, L);
+            if (adj > best_adj) {
+                best = i;
+                best_adj = adj;
+            }
+        }
+        return best;
+    }
+
+    // One Step 3 draw into `child`: tournament winner(s) and one operation.
+    void make_child(const Pop &prev) {
+        const int32_t ia = tournament(prev);
+        const uint64_t u = rng.below((uint64_t)wsum_);
+        int op = 0;
+        int64_t acc = 0;
+        for (op = 0; op < 5; ++op) {
+            acc += p_->op_weight[op];
+            if ((int64_t)u < acc) break;
+        }
+        if (op == OP_CROSSOVER) {
+            const int32_t ib = tournament(prev);
+            crossover(rng, prev.series(ia), prev.len(ia), prev.series(ib), prev.len(ib), *p_,
+                      child);
+        } else {
+            child.assign(prev.series(ia), prev.series(ia) + prev.len(ia));
+            mutate(rng, child, op, *p_, M_);
+        }
+    }
+
+    void add_penalty(const int32_t *s, int32_t L) {
+        for (int32_t t = 0; t < L; ++t) ++penalty[(size_t)s[t]];
+    }
+
+  private:
+    // base^(sum / L), the crowding penalty of a series of length L whose
+    // columns hold `sum` penalty points, memoised per (L, sum): the value is
+    // the same double std::pow returns for those arguments.
+    double penalty_pow(int64_t sum, int32_t L) {
+        if ((size_t)L >= memo_.size()) memo_.resize((size_t)L + 1);
+        std::vector<double> &t = memo_[(size_t)L];
+        if ((size_t)sum >= t.size()) t.resize(std::max<size_t>((size_t)sum + 1, 2 * t.size()), -1.0);
+        double &v = t[(size_t)sum];
+        if (!(v >= 0.0)) v = std::pow(p_->penalty_base, (double)sum / (double)L);
+        return v;
+    }
+
+    const ebic_evolve_params *p_;
+    int32_t M_;
+    int64_t wsum_ = 0;
+    std::vector<std::vector<double>> memo_;
+
+  public:
+    SplitMix64 rng;
+    std::vector<int32_t> penalty, child;
+};
+
 // One seeded run as a state machine, so that a driver can evaluate many
 // runs' populations together: next() builds the population of the next
 // generation (Step 1, or Steps 2-3) and says which members need scores;
@@ -368,10 +446,8 @@ inline ebic_status check_params(const ebic_evolve_params *p, int64_t n_rows, int
 class Run {
   public:
     Run(int32_t M, uint64_t seed, int32_t generations, const ebic_evolve_params &p)
-        : p_(p), M_(M), generations_(generations), rng_(seed), toprank_(M),
-          penalty_((size_t)M) {
+        : p_(p), M_(M), generations_(generations), br_(p_, M, seed), toprank_(M) {
         tabu_limit_ = p.tabu_limit < 0 ? p.population : p.tabu_limit;
-        for (int i = 0; i < 5; ++i) wsum_ += p.op_weight[i];
         evalp_ = p.eval;
         evalp_.want_masks = 0;
     }
@@ -417,10 +493,10 @@ class Run {
         cur_.clear();
         while (cur_.size() < P) {
             const int32_t L =
-                p_.len_min + (int32_t)rng_.below((uint64_t)(p_.len_max - p_.len_min + 1));
+                p_.len_min + (int32_t)br_.rng.below((uint64_t)(p_.len_max - p_.len_min + 1));
             s_.clear();
             while ((int32_t)s_.size() < L) {
-                const int32_t c = (int32_t)rng_.below((uint64_t)M_);
+                const int32_t c = (int32_t)br_.rng.below((uint64_t)M_);
                 if (!contains(s_, c)) s_.push_back(c);
             }
             if (!tabu_.insert(s_.data(), L)) continue;
@@ -429,42 +505,11 @@ class Run {
         first_ = 0;
     }
 
-    // Tournament over the previous population with the crowding penalty.
-    int32_t tournament() {
-        int32_t best = -1;
-        double best_adj = -INFINITY;
-        for (int32_t r = 0; r < p_.tournament; ++r) {
-            const int32_t i = (int32_t)rng_.below((uint64_t)prev_.size());
-            const int32_t *si = prev_.series(i);
-            const int32_t L = prev_.len(i);
-            int64_t sum = 0;
-            for (int32_t t = 0; t < L; ++t) sum += penalty_[(size_t)si[t]];
-            const double adj = prev_.fit[(size_t)i] / penalty_pow(sum, L);
-            if (adj > best_adj) {
-                best = i;
-                best_adj = adj;
-            }
-        }
-        return best;
-    }
-
-    // base^(sum / L), the crowding penalty of a series of length L whose
-    // columns hold `sum` penalty points, memoised per (L, sum): the value is
-    // the same double std::pow returns for those arguments.
-    double penalty_pow(int64_t sum, int32_t L) {
-        if ((size_t)L >= pow_memo_.size()) pow_memo_.resize((size_t)L + 1);
-        std::vector<double> &t = pow_memo_[(size_t)L];
-        if ((size_t)sum >= t.size()) t.resize(std::max<size_t>((size_t)sum + 1, 2 * t.size()), -1.0);
-        double &v = t[(size_t)sum];
-        if (!(v >= 0.0)) v = std::pow(p_.penalty_base, (double)sum / (double)L);
-        return v;
-    }
-
     // Step 2: elites from the top-rank list, penalties of their columns.
     void elitism() {
         const int32_t P = p_.population;
         const std::vector<TopEntry> &top = toprank_.entries();
-        std::fill(penalty_.begin(), penalty_.end(), 0);
+        std::fill(br_.penalty.begin(), br_.penalty.end(), 0);
         cur_.clear();
         const int32_t n_e = (int32_t)std::min<int64_t>(
             (int64_t)top.size(), (int64_t)P * p_.elite_num / p_.elite_den);
@@ -473,61 +518,50 @@ class Run {
             cur_.push(te.s.data(), (int32_t)te.s.size());
             cur_.counts.push_back(te.count);
             cur_.fit.push_back(te.fit);
-            for (int32_t c : te.s) ++penalty_[(size_t)c];
+            br_.add_penalty(te.s.data(), (int32_t)te.s.size());
         }
         first_ = n_e;
-    }
-
-    // One Step 3 draw into child_: tournament winner(s) and one operation.
-    void make_child() {
-        const int32_t ia = tournament();
-        const uint64_t u = rng_.below((uint64_t)wsum_);
-        int op = 0;
-        int64_t acc = 0;
-        for (op = 0; op < 5; ++op) {
-            acc += p_.op_weight[op];
-            if ((int64_t)u < acc) break;
-        }
-        if (op == OP_CROSSOVER) {
-            const int32_t ib = tournament();
-            crossover(rng_, prev_.series(ia), prev_.len(ia), prev_.series(ib), prev_.len(ib), p_,
-                      child_);
-        } else {
-            child_.assign(prev_.series(ia), prev_.series(ia) + prev_.len(ia));
-            mutate(rng_, child_, op, p_, M_);
-        }
     }
 
     // Steps 2-3: elitism, penalties and novel children.
     void breed() {
         elitism();
         int32_t hits = 0;
+        const std::vector<int32_t> &child = br_.child;
         while (cur_.size() < p_.population) {
-            make_child();
-            const int32_t L = (int32_t)child_.size();
-            if (!tabu_.insert(child_.data(), L)) {
+            br_.make_child(prev_);
+            const int32_t L = (int32_t)child.size();
+            if (!tabu_.insert(child.data(), L)) {
                 if (++hits > tabu_limit_) {
                     stopped_ = true;
                     return;
                 }
                 continue;
             }
-            cur_.push(child_.data(), L);
-            for (int32_t c : child_) ++penalty_[(size_t)c];
+            cur_.push(child.data(), L);
+            br_.add_penalty(child.data(), L);
         }
     }
 
   public:
     // Screened Steps 2-3 (offspring screening by a surrogate; not in the
-    // paper): after elitism, draw oversample x (P - elites) children exactly
-    // like Step 3 -- novel with respect to the tabu list and to each other,
-    // each adding to its columns' penalties -- then keep the P - elites
-    // children that `score` ranks highest (ties: earlier child first).  Only
-    // the kept children enter the tabu list.  A draw that repeats a known or
-    // pooled series is a hit; more than tabu_limit x oversample hits stop the
-    // run.  `score(pool)` returns one value per pooled child.
+    // paper).  After elitism, kScreenShares breeders draw a pool of
+    // oversample x (P - elites) children in parallel.  Breeder j draws an
+    // equal share with a stream seeded by the j-th of kScreenShares draws
+    // from the run's stream, starting from the elites' penalties and adding
+    // its own children's (Step 3 within the share); it keeps children novel
+    // with respect to the tabu list and to its share.  The shares are joined
+    // in breeder order, dropping series an earlier share holds; should the
+    // pool fall short of P - elites, the run's own breeder tops it up.  The
+    // P - elites children that `score` ranks highest (ties: earlier child
+    // first) are kept and enter the tabu list.  A draw that repeats a known
+    // or pooled series is a hit; more than tabu_limit x oversample hits in a
+    // generation stop the run.  `score(pool)` returns one value per pooled
+    // child.  The outcome depends on neither the thread count nor timing.
+    static constexpr int32_t kScreenShares = 16;
+
     template <typename Scorer>
-    bool next_screened(int32_t oversample, Scorer &&score) {
+    bool next_screened(int32_t oversample, Scorer &&score, int32_t threads = 0) {
         if (gen_ == 0) {
             initial();
             return true;
@@ -535,31 +569,67 @@ class Run {
         if (gen_ > generations_ || stopped_) return false;
         elitism();
         const int32_t need = p_.population - first_;
+        const int64_t target = (int64_t)need * oversample;
         const int64_t limit = (int64_t)tabu_limit_ * oversample;
+        struct Share {
+            uint64_t seed = 0;
+            Pop pop;
+            int64_t hits = 0;
+        };
+        std::vector<Share> shares((size_t)kScreenShares);
+        for (Share &sh : shares) sh.seed = br_.rng.next();
+        auto draw = [&](int32_t j) {
+            Share &sh = shares[(size_t)j];
+            const int64_t quota = target / kScreenShares + (j < target % kScreenShares ? 1 : 0);
+            Breeder b(p_, M_, sh.seed);
+            b.penalty = br_.penalty;
+            Tabu mine;
+            while (sh.pop.size() < quota) {
+                b.make_child(prev_);
+                const int32_t L = (int32_t)b.child.size();
+                if (tabu_.contains(b.child.data(), L) || !mine.insert(b.child.data(), L)) {
+                    if (++sh.hits > limit) return;
+                    continue;
+                }
+                sh.pop.push(b.child.data(), L);
+                b.add_penalty(b.child.data(), L);
+            }
+        };
+        run_shares(kScreenShares, threads, draw);
+        int64_t hits = 0;
         pool_.clear();
         Tabu pooled;
-        int64_t hits = 0;
-        while (pool_.size() < (int64_t)need * oversample) {
-            make_child();
-            const int32_t L = (int32_t)child_.size();
-            if (tabu_.contains(child_.data(), L) || !pooled.insert(child_.data(), L)) {
-                if (++hits > limit) {
-                    stopped_ = true;
-                    return false;
-                }
+        for (const Share &sh : shares) {
+            hits += sh.hits;
+            for (int32_t i = 0; i < sh.pop.size(); ++i) {
+                if (pooled.insert(sh.pop.series(i), sh.pop.len(i)))
+                    pool_.push(sh.pop.series(i), sh.pop.len(i));
+                else
+                    ++hits;
+            }
+        }
+        const std::vector<int32_t> &child = br_.child;
+        while (hits <= limit && pool_.size() < need) {
+            br_.make_child(prev_);
+            const int32_t L = (int32_t)child.size();
+            if (tabu_.contains(child.data(), L) || !pooled.insert(child.data(), L)) {
+                ++hits;
                 continue;
             }
-            pool_.push(child_.data(), L);
-            for (int32_t c : child_) ++penalty_[(size_t)c];
+            pool_.push(child.data(), L);
         }
-        std::vector<float> s = score(pool_);
+        if (hits > limit) {
+            stopped_ = true;
+            return false;
+        }
+        std::vector<float> sc = score(pool_);
         std::vector<int32_t> order((size_t)pool_.size());
         for (int32_t i = 0; i < pool_.size(); ++i) {
             order[(size_t)i] = i;
-            if (s[(size_t)i] != s[(size_t)i]) s[(size_t)i] = -INFINITY;  // NaN ranks last
+            if (sc[(size_t)i] != sc[(size_t)i]) sc[(size_t)i] = -INFINITY;  // NaN ranks last
         }
         std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return s[(size_t)a] > s[(size_t)b]; });
+                         [&](int32_t a, int32_t b) { return sc[(size_t)a] > sc[(size_t)b]; });
         order.resize((size_t)need);
         std::sort(order.begin(), order.end());
         for (int32_t i : order) {
@@ -569,18 +639,38 @@ class Run {
         return true;
     }
 
+    Run(const Run &) = delete;
+    Run &operator=(const Run &) = delete;
+
+  private:
+    // Runs f(0) .. f(n - 1) on up to `threads` threads (0: the hardware's).
+    template <typename F>
+    static void run_shares(int32_t n, int32_t threads, F &&f) {
+        if (threads <= 0) threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
+        threads = std::min(threads, n);
+        if (threads <= 1) {
+            for (int32_t i = 0; i < n; ++i) f(i);
+            return;
+        }
+        std::atomic<int32_t> next{0};
+        std::vector<std::thread> pool;
+        for (int32_t t = 0; t < threads; ++t)
+            pool.emplace_back([&] {
+                for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
+            });
+        for (std::thread &th : pool) th.join();
+    }
+
   private:
     const ebic_evolve_params p_;
     const int32_t M_;
     const int32_t generations_;
-    SplitMix64 rng_;
+    Breeder br_;
     Tabu tabu_;
     TopRank toprank_;
-    std::vector<int32_t> penalty_, s_, child_;
-    std::vector<std::vector<double>> pow_memo_;
+    std::vector<int32_t> s_;
     Pop prev_, cur_, pool_;
     ebic_params evalp_{};
-    int64_t wsum_ = 0;
     int32_t tabu_limit_ = 0;
     int32_t gen_ = 0, first_ = 0, gens_run_ = 0;
     bool stopped_ = false;
