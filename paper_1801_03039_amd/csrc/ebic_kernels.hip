@@ -161,6 +161,27 @@ __global__ __launch_bounds__(kBlock) void tie_flags_kernel(const uint64_t *__res
 constexpr int kShareShift = 33;
 constexpr uint64_t kBadBit = 1ull << 32;
 
+// Count and Eq. (1) fitness of candidate c (count -1 and NaN fitness for a
+// malformed candidate).
+template <typename LogPtr>
+__device__ __forceinline__ void write_result(int64_t c, int32_t total, bool bad, int32_t L,
+                                             int32_t sigma, LogPtr logt,
+                                             int32_t *__restrict__ counts,
+                                             double *__restrict__ fitness) {
+    if (bad) {
+        counts[c] = -1;
+        fitness[c] = __builtin_nan("");
+        return;
+    }
+    counts[c] = total;
+    double f = 0.0;
+    if (total > 1) {
+        const int32_t e = total - sigma < 0 ? total - sigma : 0;
+        f = ldexp((double)L * logt[total - 1], e);
+    }
+    fitness[c] = f;
+}
+
 template <typename LogPtr>
 __device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, int64_t share,
                                             int64_t parts, int32_t L, int32_t sigma,
@@ -174,19 +195,7 @@ __device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, i
     const unsigned long long now = before + add;
     if ((int64_t)(now >> kShareShift) != parts) return;
     atomicExch(acc + c, 0ull);
-    if (now & kBadBit) {
-        counts[c] = -1;
-        fitness[c] = __builtin_nan("");
-        return;
-    }
-    const int32_t total = (int32_t)(uint32_t)now;
-    counts[c] = total;
-    double f = 0.0;
-    if (total > 1) {
-        const int32_t e = total - sigma < 0 ? total - sigma : 0;
-        f = ldexp((double)L * logt[total - 1], e);
-    }
-    fitness[c] = f;
+    write_result(c, (int32_t)(uint32_t)now, (now & kBadBit) != 0, L, sigma, logt, counts, fitness);
 }
 
 // ------------------------------------------------------- direct evaluator --
@@ -282,8 +291,10 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 
 // -------------------------------------------------------- index evaluator --
 //
-// Thread = (candidate c, 64-row word w), flattened c-major over the grid, so
-// every lane has work whatever W is.  The workgroup first stages the CBF
+// Thread = (candidate c, V consecutive 64-row words), c-major, so every
+// lane has work whatever W is; the V words share the lane's column reads and
+// loop, and are read with 16-byte loads when V > 1 (fewer waves, more loads
+// in flight per lane, the same bytes).  The workgroup first stages the CBF
 // columns of the candidates it covers in LDS.  Per consecutive pair (p, q) a
 // lane reads lt(p,q) -- and lt(q,p) for the falling direction -- from the
 // pairwise order index and folds the violation words (complements) into K+1
@@ -295,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
 // every enabled direction.
 constexpr int kIdxLds = 4096;   // staged column entries per workgroup
 constexpr int kUnroll = 4;   // pairs per batch of loads (single-run default)
-constexpr int kWordsPerLane = 1;   // 64-row words per lane (single-run kernel)
+constexpr int kWordsPerLane = 2;   // 64-row words per lane (flattened single-run tiling)
 
 template <int K, bool NEG>
 __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1], uint64_t lt_pq,
@@ -329,12 +340,20 @@ __device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)
     }
 }
 
-// One tile (kBlock consecutive items) of one run.  An item is a candidate
-// and V consecutive 64-row words of it (V words per lane share the lane's
-// column reads and loop).  Shared by the single-run kernel (tile =
-// workgroup) and the persistent multi-run kernel.
-template <int K, bool NEG, int U, int V>
-__device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
+// One tile of one run.  An item is a candidate and V consecutive 64-row
+// words of it (V words per lane share the lane's column reads and loop).
+// Two tilings:
+//   ALIGNED = false: kBlock consecutive items of the flattened (candidate,
+//     item) order; a candidate may span workgroups, so each workgroup adds
+//     its share of a candidate's count with one packed global atomic and the
+//     last share writes the result (finish_part).  Shared by the single-run
+//     kernel and the persistent multi-run kernel.
+//   ALIGNED = true: the workgroup holds `cpw` whole candidates (requires
+//     ceil(W / V) <= kBlock); counts are summed with LDS atomics and the
+//     first lane of each candidate writes its result after a workgroup
+//     barrier -- no global atomics and no accumulator scratch.
+template <int K, bool NEG, int U, int V, bool ALIGNED>
+__device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uint32_t cpw,
                                            const int32_t *__restrict__ offsets,
                                            const int32_t *__restrict__ cols, int64_t n_entries,
                                            int32_t sigma, uint64_t *__restrict__ masks,
@@ -351,11 +370,24 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     const int tid = threadIdx.x, lane = tid & 63;
     // The launcher guarantees P * ceil(W / V) < 2^32.
     const uint32_t Wg = (uint32_t)((W + V - 1) / V);   // items per candidate
-    const uint32_t item = tile * (uint32_t)kBlock + (uint32_t)tid;
-    const uint32_t total = (uint32_t)P * Wg;
-    const bool active = item < total;
-    const uint32_t cl = active ? item / Wg : (uint32_t)P - 1;   // candidate within the run
-    const uint32_t g = active ? item - cl * Wg : 0;
+    uint32_t cl, g, c_lo, c_hi, slot = 0;
+    bool active;
+    if constexpr (ALIGNED) {
+        slot = (uint32_t)tid / Wg;                                // candidate slot in the tile
+        c_lo = tile * cpw;
+        c_hi = min(c_lo + cpw, (uint32_t)P) - 1;
+        active = slot < cpw && c_lo + slot < (uint32_t)P;
+        cl = active ? c_lo + slot : c_hi;
+        g = active ? (uint32_t)tid - slot * Wg : 0;
+    } else {
+        const uint32_t item = tile * (uint32_t)kBlock + (uint32_t)tid;
+        active = item < (uint32_t)P * Wg;
+        cl = active ? item / Wg : (uint32_t)P - 1;               // candidate within the run
+        g = active ? item - cl * Wg : 0;
+        const uint32_t i0 = tile * (uint32_t)kBlock;
+        c_lo = i0 / Wg;
+        c_hi = min((i0 + kBlock - 1) / Wg, (uint32_t)P - 1);
+    }
     const int64_t w0 = (int64_t)g * V;                           // first word of the item
     const int64_t c = R.cand_base + cl;                          // candidate in the launch
 
@@ -367,15 +399,19 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
     // every lane's series lies inside the staged span (always, for a
     // well-formed CBF); otherwise the whole workgroup reads them from global
     // memory.  The choice is uniform over the workgroup.
-    const uint32_t i0 = tile * (uint32_t)kBlock;
-    const uint32_t c_lo = i0 / Wg;
-    const uint32_t c_hi = min((i0 + kBlock - 1) / Wg, (uint32_t)P - 1);
     const int64_t b0 = offsets[R.cand_base + c_lo], b1 = offsets[R.cand_base + c_hi + 1];
+    __shared__ int32_t s_rows[ALIGNED ? kBlock : 1];
+    __shared__ int32_t s_bad[ALIGNED ? kBlock : 1];
+    if (ALIGNED && (uint32_t)tid < cpw) {
+        s_rows[tid] = 0;
+        s_bad[tid] = 0;
+    }
     const bool span_ok = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
     const bool lane_ok = !ok_range || (start >= b0 && end <= b1);
     const bool use_lds = __syncthreads_and(span_ok && lane_ok) != 0;
     if (use_lds) {
-        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += kBlock) s_cols[e] = cols[b0 + e];
+        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += (int32_t)blockDim.x)
+            s_cols[e] = cols[b0 + e];
         __syncthreads();
     }
     const int32_t lds0 = (int32_t)(start - b0);
@@ -493,6 +529,19 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
         }
     }
 
+    if constexpr (ALIGNED) {
+        // The staging barrier above ordered the zeroing of s_rows/s_bad
+        // before these updates.
+        if (active) {
+            atomicAdd(&s_rows[slot], rows);
+            if (bad) s_bad[slot] = 1;
+        }
+        __syncthreads();
+        if (active && g == 0)
+            write_result(c, s_rows[slot], s_bad[slot] != 0, L, sigma, logt, counts, fitness);
+        return;
+    }
+
     // Segmented sum over lanes of the same candidate (lanes hold consecutive
     // items, so each candidate is one contiguous run of lanes): the run's
     // head gets the run's row count (low 16 bits, <= 64*64*V) and its number
@@ -515,14 +564,14 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile,
                     counts, fitness);
 }
 
-template <int K, bool NEG, int U, int V>
+template <int K, bool NEG, int U, int V, bool ALIGNED>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
-    IndexRun R, const int32_t *__restrict__ offsets, const int32_t *__restrict__ cols,
-    int64_t n_entries, int32_t sigma, uint64_t *__restrict__ masks,
-    unsigned long long *__restrict__ acc, int32_t *__restrict__ counts,
-    double *__restrict__ fitness) {
-    index_tile<K, NEG, U, V>(R, blockIdx.x, offsets, cols, n_entries, sigma, masks, acc, counts,
-                             fitness);
+    IndexRun R, uint32_t cpw, const int32_t *__restrict__ offsets,
+    const int32_t *__restrict__ cols, int64_t n_entries, int32_t sigma,
+    uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
+    int32_t *__restrict__ counts, double *__restrict__ fitness) {
+    index_tile<K, NEG, U, V, ALIGNED>(R, blockIdx.x, cpw, offsets, cols, n_entries, sigma, masks,
+                                      acc, counts, fitness);
 }
 
 // --------------------------------------------------- batched (many runs) --
@@ -565,8 +614,8 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
         const uint32_t t = s_tile;
         if (t >= total_tiles) break;  // uniform
         const int32_t r = s_run;
-        index_tile<K, NEG, U, 1>(runs[r], t - tile_base[r], offsets, cols, n_entries, sigma,
-                                 masks, acc, counts, fitness);
+        index_tile<K, NEG, U, 1, false>(runs[r], t - tile_base[r], 0, offsets, cols, n_entries,
+                                        sigma, masks, acc, counts, fitness);
     }
     if (threadIdx.x == 0) {
         const unsigned left = atomicAdd(work + 1, 1u);
@@ -629,19 +678,47 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
     return hipGetLastError();
 }
 
-template <int K, int U>
-static void launch_index_k(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
-    constexpr int V = kWordsPerLane;
-    const int64_t total = (int64_t)R.P * ((R.W + V - 1) / V);
-    const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+template <int K, int U, int V, bool ALIGNED>
+static void launch_index_t(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 block,
+                           const EvalArgs &e, hipStream_t stream) {
     if (e.negative)
-        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V>), grid, dim3(kBlock), 0, stream, R,
-                           e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED>), grid, block, 0, stream, R,
+                           cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
                            e.fitness);
     else
-        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V>), grid, dim3(kBlock), 0, stream, R,
-                           e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
-                           e.fitness);
+        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V, ALIGNED>), grid, block, 0, stream,
+                           R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc,
+                           e.counts, e.fitness);
+}
+
+template <int K, int U, int V>
+static void launch_aligned(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
+    const int64_t Wg = (R.W + V - 1) / V;
+    const int64_t cpw = kBlock / Wg;
+    const int64_t threads = (cpw * Wg + kWave - 1) / kWave * kWave;
+    const dim3 grid((unsigned)((R.P + cpw - 1) / cpw));
+    launch_index_t<K, U, V, true>(R, (uint32_t)cpw, grid, dim3((unsigned)threads), e, stream);
+}
+
+// Tiling by matrix height.  Up to 1024 words (65536 rows) a workgroup holds
+// whole candidates, with the fewest words per lane (1, 2 or 4) that fit a
+// candidate in one workgroup: as many candidates per workgroup as fit, and
+// a workgroup just large enough (whole waves) to hold them.  Taller
+// matrices use the flattened tiling with 2 words per lane.
+template <int K, int U>
+static void launch_index_k(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
+    if (R.W <= kBlock)
+        launch_aligned<K, U, 1>(R, e, stream);
+    else if (R.W <= 2 * kBlock)
+        launch_aligned<K, U, 2>(R, e, stream);
+    else if (R.W <= 4 * kBlock)
+        launch_aligned<K, U, 4>(R, e, stream);
+    else {
+        constexpr int V = kWordsPerLane;
+        const int64_t total = (int64_t)R.P * ((R.W + V - 1) / V);
+        const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+        launch_index_t<K, U, V, false>(R, 0, grid, dim3(kBlock), e, stream);
+    }
 }
 
 hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,

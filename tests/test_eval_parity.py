@@ -98,6 +98,24 @@ def test_long_series_beyond_lds_stage(ebic, path):
         _check(ebic, a, pop, path, sigma=10, k=k, neg=True)
 
 
+@pytest.mark.parametrize("n", [16384, 16385, 32768, 32769, 65536, 65537])
+def test_tiling_boundary_row_counts(ebic, n):
+    # The index evaluator holds whole candidates per workgroup with 1, 2 or
+    # 4 words per lane up to 16384, 32768 and 65536 rows, and spreads
+    # taller matrices over workgroups; both sides of each switch, with
+    # planted rows.
+    rng = np.random.default_rng(n)
+    m = 24
+    a = rng.standard_normal((n, m)).astype(np.float32)
+    rows = rng.choice(n, size=300, replace=False)
+    order = rng.permutation(m)[:8]
+    a[np.ix_(rows, order)] = np.sort(a[np.ix_(rows, order)], axis=1)
+    pop = synth.random_population(rng, m, 150, 2, 10) + [list(order), list(order[:5])]
+    for k, neg in ((0, False), (1, True)):
+        _note(f"tiling boundary n={n} k={k} neg={neg}")
+        _check(ebic, a, pop, "index", sigma=50, k=k, neg=neg)
+
+
 @pytest.mark.parametrize("name", ["tiny", "expression", "wide"])
 @pytest.mark.parametrize("path", PATHS)
 def test_workload_populations(ebic, name, path):

@@ -101,7 +101,7 @@ def test_mask_rows_capacity_and_empty(E):
     off, rows = E.mask_rows(_dev(masks), n, capacity=cap)
     assert torch.equal(off, full_off)
     assert torch.equal(rows, full_rows[:cap])
-    off0, rows0 = E.mask_rows(_dev(np.zeros((0, 2, 5), np.uint64)), n=300)
+    off0, rows0 = E.mask_rows(_dev(np.zeros((0, 2, 5), np.uint64)), 300)
     assert off0.cpu().tolist() == [0] and rows0.numel() == 0
     offz, rowsz = E.mask_rows(_dev(np.zeros((4, 0), np.uint64)), 0)
     assert offz.cpu().tolist() == [0] * 5 and rowsz.numel() == 0
