@@ -360,9 +360,10 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
  * learned per-column embeddings (not in the paper; it only ranks
  * candidates, every admitted candidate is still scored exactly).
  *
- *   x    = [ mean over the series of E[c_t] ;
+ *   x    = [ mean over the series of E[c_t] + Z[L] ;
  *            mean over consecutive pairs of F[c_t] * T[c_{t+1}] (0 if L = 1) ]
- *          (E, F, T: embed_dim each; the pair term makes the model see order)
+ *          (E, F, T, Z: embed_dim each; the pair term makes the model see
+ *          order, Z the series length L)
  *   h1   = relu(W1 bf16(x) + b1)        W1: hidden x (2 embed_dim)
  *   h2   = relu(W2 bf16(h1) + b2)       W2: hidden x hidden
  *   y    = w3 . bf16(h2) + b3           w3: hidden
@@ -370,7 +371,7 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
  * FP32 accumulation; training minimises (1/B) sum (y - target)^2 with Adam
  * on the masters (gradients pass through the BF16 casts unchanged).
  * Parameters, flattened FP32 in this order: E, F, T [n_cols][embed_dim]
- * each, W1 [hidden][2 embed_dim], b1 [hidden], W2 [hidden][hidden],
+ * each, Z [n_cols + 1][embed_dim], W1 [hidden][2 embed_dim], b1 [hidden], W2 [hidden][hidden],
  * b2 [hidden], w3 [hidden], b3 [1].  All reductions run in a fixed order, so results are
  * deterministic on a given device.  Errors: message via ebic_last_error(NULL).
  */
@@ -383,7 +384,7 @@ typedef struct {
 } ebic_mlp_config;
 
 void ebic_mlp_defaults(ebic_mlp_config *c);
-/* Parameters initialised from SplitMix64(seed): E, F, T ~ U(-1,1), W1 ~
+/* Parameters initialised from SplitMix64(seed): E, F, T ~ U(-1,1), Z = 0, W1 ~
  * U(+-sqrt(6/(2 embed_dim))), W2 ~ U(+-sqrt(6/hidden)), w3 ~
  * U(+-sqrt(3/hidden)), biases 0. */
 ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t seed,
@@ -392,13 +393,19 @@ ebic_status ebic_mlp_destroy(ebic_mlp *m);
 int64_t ebic_mlp_param_count(const ebic_mlp *m);
 ebic_status ebic_mlp_get_params(const ebic_mlp *m, float *params);
 ebic_status ebic_mlp_set_params(ebic_mlp *m, const float *params);   /* also resets Adam */
-/* Host CBF in, host outputs, blocking.  Columns must lie in [0, n_cols). */
+/* Host CBF in, host outputs, blocking.  Columns must lie in [0, n_cols) and
+ * series hold 1 to n_cols entries (E_RANGE otherwise). */
 ebic_status ebic_mlp_predict(ebic_mlp *m, const int32_t *offsets, const int32_t *cols, int32_t B,
                              float *y);
 ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
                                int32_t B, const float *target, float *grad, float *loss);
 ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
                                 int32_t B, const float *target, float *loss);
+/* `steps` Adam steps on one batch (uploaded once); *loss (may be NULL)
+ * receives the loss before the last step.  Same result as `steps` calls of
+ * ebic_mlp_train_step on the batch. */
+ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *cols, int32_t B,
+                           const float *target, int32_t steps, float *loss);
 
 /*
  * Surrogate-screened run (not in the paper).  As ebic_evolve, except that
@@ -428,11 +435,11 @@ typedef struct {
     uint32_t struct_size;         /* sizeof(ebic_surrogate_params) */
     int32_t oversample;           /* 8 */
     int32_t warmup_generations;   /* 3 */
-    int32_t train_steps;          /* 4 */
+    int32_t train_steps;          /* 16 */
     int32_t replay_generations;   /* 4 */
-    double min_rank_corr;         /* 0.1 */
+    double min_rank_corr;         /* 0.0 */
     uint64_t mlp_seed;
-    ebic_mlp_config mlp;
+    ebic_mlp_config mlp;          /* ebic_mlp_defaults with lr 3e-3 */
     ebic_surrogate_fn on_surrogate;
     void *user;
 } ebic_surrogate_params;

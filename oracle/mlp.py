@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE (see ``oracle/__init__.py``).
 
 A 3-layer MLP over learned column embeddings, in float64:
 
-    x    = [ (1/L) sum_t E[c_t] ;
+    x    = [ (1/L) sum_t E[c_t] + Z[L] ;
              (1/(L-1)) sum_{t<L-1} F[c_t] * T[c_{t+1}]  (0 when L = 1) ]
     z1   = W1 r(x) + b1,   h1 = relu(z1)
     z2   = W2 r(h1) + b2,  h2 = relu(z2)
@@ -18,7 +18,8 @@ dW1 and dx) and treats every rounding as the identity (straight-through).
 With ``bf16=False`` the model is a plain float64 MLP, which the tests pin
 against central finite differences.
 
-Parameters are one flat vector: E, F, T [M][D] each, W1 [H][2D], b1 [H],
+Z [M+1][D] is a learned embedding of the series length L.  Parameters are
+one flat vector: E, F, T [M][D] each, Z [M+1][D], W1 [H][2D], b1 [H],
 W2 [H][H], b2 [H], w3 [H], b3 [1].
 """
 from __future__ import annotations
@@ -41,7 +42,8 @@ def split(params, M, D, H):
     p = np.asarray(params, dtype=np.float64)
     i = 0
     out = {}
-    for name, shape in (("E", (M, D)), ("F", (M, D)), ("T", (M, D)), ("W1", (H, 2 * D)),
+    for name, shape in (("E", (M, D)), ("F", (M, D)), ("T", (M, D)), ("Z", (M + 1, D)),
+                        ("W1", (H, 2 * D)),
                         ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))):
         n = int(np.prod(shape))
         out[name] = p[i:i + n].reshape(shape)
@@ -51,7 +53,7 @@ def split(params, M, D, H):
 
 
 def n_params(M, D, H):
-    return 3 * M * D + H * 2 * D + H + H * H + H + H + 1
+    return 3 * M * D + (M + 1) * D + H * 2 * D + H + H * H + H + H + 1
 
 
 def _r(x, on):
@@ -67,7 +69,7 @@ def forward(params, offsets, cols, M, D, H, bf16=True):
     x = np.zeros((B, 2 * D))
     for b in range(B):
         s = cols[offsets[b]:offsets[b + 1]]
-        x[b, :D] = P["E"][s].sum(axis=0) / len(s)
+        x[b, :D] = P["E"][s].sum(axis=0) / len(s) + P["Z"][len(s)]
         if len(s) > 1:
             x[b, D:] = (P["F"][s[:-1]] * P["T"][s[1:]]).sum(axis=0) / (len(s) - 1)
     xr = _r(x, bf16)
@@ -101,13 +103,15 @@ def loss_and_grad(params, offsets, cols, target, M, D, H, bf16=True):
     dx = dz1r @ c["W1"]
     P = c["P"]
     g_E, g_F, g_T = np.zeros((M, D)), np.zeros((M, D)), np.zeros((M, D))
+    g_Z = np.zeros((M + 1, D))
     for b in range(B):
         s = cols[offsets[b]:offsets[b + 1]]
         np.add.at(g_E, s, dx[b, :D] / len(s))
+        g_Z[len(s)] += dx[b, :D]
         if len(s) > 1:
             np.add.at(g_F, s[:-1], dx[b, D:] * P["T"][s[1:]] / (len(s) - 1))
             np.add.at(g_T, s[1:], dx[b, D:] * P["F"][s[:-1]] / (len(s) - 1))
-    grad = np.concatenate([g_E.ravel(), g_F.ravel(), g_T.ravel(), g_W1.ravel(), g_b1,
+    grad = np.concatenate([g_E.ravel(), g_F.ravel(), g_T.ravel(), g_Z.ravel(), g_W1.ravel(), g_b1,
                            g_W2.ravel(), g_b2, g_w3, g_b3])
     return loss, grad, y
 

@@ -654,7 +654,8 @@ _mlp_set_params = _sig("ebic_mlp_set_params", _i32, [_vp, _vp])
 _mlp_predict = _sig("ebic_mlp_predict", _i32, [_vp, _vp, _vp, _i32, _vp])
 _mlp_gradients = _sig("ebic_mlp_gradients", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _P(ctypes.c_float)])
 _mlp_train_step = _sig("ebic_mlp_train_step", _i32, [_vp, _vp, _vp, _i32, _vp, _P(ctypes.c_float)])
-EXPORTED += ["ebic_mlp_defaults", "ebic_mlp_create", "ebic_mlp_destroy", "ebic_mlp_param_count",
+_mlp_train = _sig("ebic_mlp_train", _i32, [_vp, _vp, _vp, _i32, _vp, _i32, _P(ctypes.c_float)])
+EXPORTED += ["ebic_mlp_train", "ebic_mlp_defaults", "ebic_mlp_create", "ebic_mlp_destroy", "ebic_mlp_param_count",
              "ebic_mlp_get_params", "ebic_mlp_set_params", "ebic_mlp_predict",
              "ebic_mlp_gradients", "ebic_mlp_train_step"]
 
@@ -728,6 +729,15 @@ class Mlp:
         loss = ctypes.c_float()
         _check(_mlp_train_step(self._h, o.ctypes.data, c.ctypes.data, B, t.ctypes.data,
                                ctypes.byref(loss)))
+        return float(loss.value)
+
+    def train(self, offsets, cols, target, steps: int) -> float:
+        """``steps`` Adam steps on one batch; returns the loss before the last."""
+        o, c, B = self._cbf(offsets, cols)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_mlp_train(self._h, o.ctypes.data, c.ctypes.data, B, t.ctypes.data, int(steps),
+                          ctypes.byref(loss)))
         return float(loss.value)
 
 

@@ -25,14 +25,14 @@ struct ebic_mlp {
     int32_t M = 0, D = 0, H = 0;
     ebic_mlp_config cfg{};
     int64_t n_params = 0;
-    int64_t oE = 0, oF = 0, oT = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, ow3 = 0, ob3 = 0;
+    int64_t oE = 0, oF = 0, oT = 0, oZ = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, ow3 = 0, ob3 = 0;
     float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
     uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;
     int64_t step = 0;
     // per-batch buffers (capacity cap_B candidates, cap_L column entries)
     int64_t cap_B = 0, cap_L = 0;
     int32_t *off = nullptr, *cols = nullptr, *occ_start = nullptr, *occ_pos = nullptr,
-            *occ_b = nullptr;
+            *occ_b = nullptr, *len_start = nullptr, *len_b = nullptr;
     float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *y = nullptr, *t = nullptr, *dy = nullptr,
           *sq = nullptr, *dZ2 = nullptr, *G1 = nullptr, *dZ1 = nullptr, *dX = nullptr;
     uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
@@ -89,6 +89,7 @@ ebic_status reserve(ebic_mlp *m, int64_t B, int64_t L) {
         MHIP(dalloc(m->dZ1, c * H));
         MHIP(dalloc(m->dZ1b, c * H));
         MHIP(dalloc(m->dX, c * 2 * D));
+        MHIP(dalloc(m->len_b, c));
         m->cap_B = c;
     }
     if (L > m->cap_L) {
@@ -112,7 +113,7 @@ int32_t splits_for(int32_t B) { return std::max(1, std::min(kMaxSplits, B / 256)
 bool check_cbf(const ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t B) {
     if (off[0] != 0) return false;
     for (int32_t b = 0; b < B; ++b) {
-        if (off[b + 1] <= off[b]) return false;
+        if (off[b + 1] <= off[b] || off[b + 1] - off[b] > m->M) return false;
         for (int32_t i = off[b]; i < off[b + 1]; ++i)
             if (cols[i] < 0 || cols[i] >= m->M) return false;
     }
@@ -123,7 +124,7 @@ bool check_cbf(const ebic_mlp *m, const int32_t *off, const int32_t *cols, int32
 ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t B,
                    const float *target, bool occurrences) {
     if (!off || !cols || B < 1) return mfail(EBIC_E_ARG, "need a non-empty CBF batch");
-    if (!check_cbf(m, off, cols, B)) return mfail(EBIC_E_RANGE, "malformed CBF or column out of range");
+    if (!check_cbf(m, off, cols, B)) return mfail(EBIC_E_RANGE, "malformed CBF, a series longer than n_cols or a column out of range");
     const int64_t L = off[B];
     ebic_status st = reserve(m, B, L);
     if (st != EBIC_OK) return st;
@@ -147,12 +148,22 @@ ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t
                 pos[(size_t)k] = i;
                 occ[(size_t)k] = b;
             }
+        // CSR by series length: the candidates of length l, in order.
+        std::vector<int32_t> lstart((size_t)m->M + 2, 0), lb((size_t)B);
+        for (int32_t b = 0; b < B; ++b) ++lstart[(size_t)(off[b + 1] - off[b]) + 1];
+        for (int32_t l = 0; l <= m->M; ++l) lstart[(size_t)l + 1] += lstart[(size_t)l];
+        std::vector<int32_t> lfill(lstart.begin(), lstart.end() - 1);
+        for (int32_t b = 0; b < B; ++b) lb[(size_t)lfill[(size_t)(off[b + 1] - off[b])]++] = b;
         if (!m->occ_start) MHIP(hipMalloc((void **)&m->occ_start, sizeof(int32_t) * ((size_t)m->M + 1)));
+        if (!m->len_start) MHIP(hipMalloc((void **)&m->len_start, sizeof(int32_t) * ((size_t)m->M + 2)));
         MHIP(hipStreamSynchronize(m->stream));  // no kernel still reads the previous lists
         MHIP(hipMemcpy(m->occ_start, start.data(), sizeof(int32_t) * start.size(),
                        hipMemcpyHostToDevice));
         MHIP(hipMemcpy(m->occ_pos, pos.data(), sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice));
         MHIP(hipMemcpy(m->occ_b, occ.data(), sizeof(int32_t) * (size_t)L, hipMemcpyHostToDevice));
+        MHIP(hipMemcpy(m->len_start, lstart.data(), sizeof(int32_t) * lstart.size(),
+                       hipMemcpyHostToDevice));
+        MHIP(hipMemcpy(m->len_b, lb.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice));
     }
     return EBIC_OK;
 }
@@ -161,8 +172,8 @@ ebic_status forward(ebic_mlp *m, int32_t B) {
     const int32_t D = m->D, H = m->H;
     hipStream_t s = m->stream;
     const int32_t D2 = 2 * D;
-    MHIP(mlp::pool_fwd(m->p + m->oE, m->p + m->oF, m->p + m->oT, D, m->off, m->cols, B, m->X,
-                       m->Xb, s));
+    MHIP(mlp::pool_fwd(m->p + m->oE, m->p + m->oF, m->p + m->oT, m->p + m->oZ, D, m->off,
+                       m->cols, B, m->X, m->Xb, s));
     mlp::Gemm l1{m->Xb, D2, 1, m->W1b, 1, D2, B, H, D2, 1, m->p + m->ob1, 1, m->Z1, m->H1b, nullptr};
     MHIP(mlp::gemm(l1, s));
     mlp::Gemm l2{m->H1b, H, 1, m->W2b, 1, H, B, H, H, 1, m->p + m->ob2, 1, m->Z2, m->H2b, nullptr};
@@ -197,6 +208,7 @@ ebic_status backward(ebic_mlp *m, int32_t B) {
     MHIP(mlp::gemm(gx, s));
     MHIP(mlp::pool_bwd(m->dX, D, m->p + m->oF, m->p + m->oT, m->off, m->cols, m->occ_start,
                        m->occ_pos, m->occ_b, m->M, g + m->oE, g + m->oF, g + m->oT, s));
+    MHIP(mlp::len_bwd(m->dX, D, m->len_start, m->len_b, m->M + 1, g + m->oZ, s));
     return EBIC_OK;
 }
 
@@ -260,7 +272,8 @@ ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t
     m->oE = 0;
     m->oF = m->oE + M * D;
     m->oT = m->oF + M * D;
-    m->oW1 = m->oT + M * D;
+    m->oZ = m->oT + M * D;
+    m->oW1 = m->oZ + (M + 1) * D;
     m->ob1 = m->oW1 + H * 2 * D;
     m->oW2 = m->ob1 + H;
     m->ob2 = m->oW2 + H * H;
@@ -303,7 +316,7 @@ ebic_status ebic_mlp_destroy(ebic_mlp *m) {
     (void)hipSetDevice(m->device);
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     void *bufs[] = {m->p, m->g, m->m1, m->m2, m->W1b, m->W2b, m->w3b, m->off, m->cols,
-                    m->occ_start, m->occ_pos, m->occ_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
+                    m->occ_start, m->occ_pos, m->occ_b, m->len_start, m->len_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
                     m->dZ2, m->G1, m->dZ1, m->dX, m->Xb, m->H1b, m->H2b, m->dZ2b, m->dZ1b, m->ws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -363,23 +376,31 @@ ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_
     return EBIC_OK;
 }
 
-ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
-                                int32_t B, const float *target, float *loss) {
+ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *cols, int32_t B,
+                           const float *target, int32_t steps, float *loss) {
     if (!m || !target) return mfail(EBIC_E_ARG, "null argument");
+    if (steps < 1) return mfail(EBIC_E_ARG, "steps must be >= 1");
     MHIP(hipSetDevice(m->device));
     ebic_status st = upload(m, offsets, cols, B, target, true);
     if (st != EBIC_OK) return st;
-    if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
-    m->step += 1;
-    const float c1 = 1.f - std::pow(m->cfg.beta1, (float)m->step);
-    const float c2 = 1.f - std::pow(m->cfg.beta2, (float)m->step);
-    MHIP(mlp::adam(m->p, m->g, m->m1, m->m2, m->n_params, m->cfg.lr, m->cfg.beta1, m->cfg.beta2,
-                   m->cfg.eps, c1, c2, m->stream));
-    if ((st = refresh_bf16(m)) != EBIC_OK) return st;
-    const float l = host_loss(m, B, &st);  // loss of the pre-step parameters
+    for (int32_t k = 0; k < steps; ++k) {
+        if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
+        m->step += 1;
+        const float c1 = 1.f - std::pow(m->cfg.beta1, (float)m->step);
+        const float c2 = 1.f - std::pow(m->cfg.beta2, (float)m->step);
+        MHIP(mlp::adam(m->p, m->g, m->m1, m->m2, m->n_params, m->cfg.lr, m->cfg.beta1,
+                       m->cfg.beta2, m->cfg.eps, c1, c2, m->stream));
+        if ((st = refresh_bf16(m)) != EBIC_OK) return st;
+    }
+    const float l = host_loss(m, B, &st);  // loss before the last step
     if (st != EBIC_OK) return st;
     if (loss) *loss = l;
     return EBIC_OK;
+}
+
+ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
+                                int32_t B, const float *target, float *loss) {
+    return ebic_mlp_train(m, offsets, cols, B, target, 1, loss);
 }
 
 }  // extern "C"

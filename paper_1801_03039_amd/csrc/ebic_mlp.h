@@ -25,8 +25,13 @@ struct Gemm {
     float *ws;             // splits > 1
 };
 
-hipError_t pool_fwd(const float *E, const float *F, const float *T, int32_t D, const int32_t *off,
-                    const int32_t *cols, int32_t B, float *X, uint16_t *Xb, hipStream_t s);
+hipError_t pool_fwd(const float *E, const float *F, const float *T, const float *Zl, int32_t D,
+                    const int32_t *off, const int32_t *cols, int32_t B, float *X, uint16_t *Xb,
+                    hipStream_t s);
+// dZl[l][d] = sum over the candidates b of length l (CSR len_start/len_b)
+// of dX[b][d], for l < n_len.
+hipError_t len_bwd(const float *dX, int32_t D, const int32_t *len_start, const int32_t *len_b,
+                   int32_t n_len, float *dZl, hipStream_t s);
 hipError_t pool_bwd(const float *dX, int32_t D, const float *F, const float *T, const int32_t *off,
                     const int32_t *cols, const int32_t *occ_start, const int32_t *occ_pos,
                     const int32_t *occ_b, int32_t M, float *dE, float *dF, float *dT,

@@ -45,7 +45,8 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 // series order.  Xb = bf16(X).  X is B x 2D.
 __global__ __launch_bounds__(kBlock) void pool_fwd_kernel(const float *__restrict__ E,
                                                           const float *__restrict__ F,
-                                                          const float *__restrict__ T, int32_t D,
+                                                          const float *__restrict__ T,
+                                                          const float *__restrict__ Zl, int32_t D,
                                                           const int32_t *__restrict__ off,
                                                           const int32_t *__restrict__ cols,
                                                           int32_t B, float *__restrict__ X,
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void pool_fwd_kernel(const float *__restric
     if (d < D) {
         float acc = 0.f;
         for (int32_t t = s; t < e; ++t) acc += E[(int64_t)cols[t] * D + d];
-        x = acc / (float)(e - s);
+        x = acc / (float)(e - s) + Zl[(int64_t)(e - s) * D + d];
     } else if (e - s > 1) {
         const int32_t dd = d - D;
         float acc = 0.f;
@@ -106,6 +107,22 @@ __global__ __launch_bounds__(kBlock) void pool_bwd_kernel(const float *__restric
     dE[i] = ge;
     dF[i] = gf;
     dT[i] = gt;
+}
+
+// Gradient of the length embedding: dZ[l] = sum of dX[b][0:D] over the
+// candidates of length l (len_b[len_start[l] .. len_start[l+1]), in
+// candidate order).
+__global__ __launch_bounds__(kBlock) void len_bwd_kernel(const float *__restrict__ dX, int32_t D,
+                                                         const int32_t *__restrict__ len_start,
+                                                         const int32_t *__restrict__ len_b,
+                                                         int32_t n_len, float *__restrict__ dZl) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (int64_t)n_len * D) return;
+    const int32_t l = (int32_t)(i / D), d = (int32_t)(i - (int64_t)l * D);
+    float acc = 0.f;
+    for (int32_t o = len_start[l]; o < len_start[l + 1]; ++o)
+        acc += dX[(int64_t)len_b[o] * 2 * D + d];
+    dZl[i] = acc;
 }
 
 // ----------------------------------------------------------------- GEMM --
@@ -343,10 +360,18 @@ inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)
 
 // ----------------------------------------------------------- launchers --
 
-hipError_t pool_fwd(const float *E, const float *F, const float *T, int32_t D, const int32_t *off,
-                    const int32_t *cols, int32_t B, float *X, uint16_t *Xb, hipStream_t s) {
-    hipLaunchKernelGGL(pool_fwd_kernel, grid1((int64_t)B * 2 * D), dim3(kBlock), 0, s, E, F, T, D,
-                       off, cols, B, X, Xb);
+hipError_t pool_fwd(const float *E, const float *F, const float *T, const float *Zl, int32_t D,
+                    const int32_t *off, const int32_t *cols, int32_t B, float *X, uint16_t *Xb,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(pool_fwd_kernel, grid1((int64_t)B * 2 * D), dim3(kBlock), 0, s, E, F, T, Zl,
+                       D, off, cols, B, X, Xb);
+    return hipGetLastError();
+}
+
+hipError_t len_bwd(const float *dX, int32_t D, const int32_t *len_start, const int32_t *len_b,
+                   int32_t n_len, float *dZl, hipStream_t s) {
+    hipLaunchKernelGGL(len_bwd_kernel, grid1((int64_t)n_len * D), dim3(kBlock), 0, s, dX, D,
+                       len_start, len_b, n_len, dZl);
     return hipGetLastError();
 }
 

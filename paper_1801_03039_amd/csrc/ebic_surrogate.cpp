@@ -76,11 +76,12 @@ void ebic_surrogate_defaults(ebic_surrogate_params *s) {
     s->struct_size = sizeof(ebic_surrogate_params);
     s->oversample = 8;
     s->warmup_generations = 3;
-    s->train_steps = 4;
+    s->train_steps = 16;
     s->replay_generations = 4;
-    s->min_rank_corr = 0.1;
+    s->min_rank_corr = 0.0;
     s->mlp_seed = 0x5EED;
     ebic_mlp_defaults(&s->mlp);
+    s->mlp.lr = 3e-3f;
 }
 
 ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generations,
@@ -179,13 +180,11 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
                 all.target.insert(all.target.end(), b.target.begin(), b.target.end());
             }
             const int32_t B = (int32_t)all.target.size();
-            for (int32_t k = 0; k < sp->train_steps; ++k) {
-                float l = 0.f;
-                if ((st = ebic_mlp_train_step(net, all.off.data(), all.cols.data(), B,
-                                              all.target.data(), &l)) != EBIC_OK)
-                    return st;
-                loss = l;
-            }
+            float l = 0.f;
+            if ((st = ebic_mlp_train(net, all.off.data(), all.cols.data(), B, all.target.data(),
+                                     sp->train_steps, &l)) != EBIC_OK)
+                return st;
+            loss = l;
         }
         if (judged) {
             last_corr = corr;

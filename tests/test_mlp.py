@@ -34,7 +34,8 @@ def _batch(rng, M, B, lmin=1, lmax=12):
 
 
 def _blocks(M, D, H):
-    sizes = [("E", M * D), ("F", M * D), ("T", M * D), ("W1", H * 2 * D), ("b1", H), ("W2", H * H),
+    sizes = [("E", M * D), ("F", M * D), ("T", M * D), ("Z", (M + 1) * D), ("W1", H * 2 * D),
+             ("b1", H), ("W2", H * H),
              ("b2", H), ("w3", H), ("b3", 1)]
     out, i = {}, 0
     for n, s in sizes:
@@ -99,3 +100,15 @@ def test_training_reduces_loss_and_is_deterministic(E):
     assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_multi_step_training_equals_single_steps(E):
+    rng = np.random.default_rng(8)
+    M, B = 70, 700
+    off, cols = _batch(rng, M, B, 2, 12)
+    t = rng.standard_normal(B).astype(np.float32)
+    with E.Mlp(M, seed=3, lr=3e-3) as a, E.Mlp(M, seed=3, lr=3e-3) as b:
+        losses = [a.train_step(off, cols, t) for _ in range(5)]
+        last = b.train(off, cols, t, 5)
+        assert np.array_equal(a.params(), b.params())
+        assert last == losses[-1]
