@@ -311,13 +311,15 @@ ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, cons
 ebic_status ebic_batch_destroy(ebic_batch *b);
 
 /* Launch shape of the persistent kernel: `workgroups` persistent
- * workgroups (0: one per resident slot) and `unroll` pairs per batch of
- * loads (2, 4 or 8). */
+ * workgroups (0: one per resident slot), `unroll` pairs per batch of loads
+ * (2, 4 or 8) and `words_per_lane` 64-row words per lane (1 or 2; a tile is
+ * 256 lanes, so 256 or 512 (candidate, word) pairs). */
 typedef struct {
     uint32_t struct_size;       /* sizeof(ebic_batch_tuning) */
     int32_t workgroups;
     int32_t unroll;
     double best_ms;             /* time of the chosen shape in the last tuning (0: untuned) */
+    int32_t words_per_lane;
 } ebic_batch_tuning;
 ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t);
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t);

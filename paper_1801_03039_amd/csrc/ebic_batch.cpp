@@ -48,7 +48,7 @@ struct ebic_batch {
     int64_t hcap_cand = 0, hcap_cols = 0;
     // launch shape and its graph
     int32_t resident_wgs = 0;       // workgroups resident at once (occupancy x CUs)
-    int32_t workgroups = 0, unroll = 4;
+    int32_t workgroups = 0, unroll = 4, words = 1;
     double tuned_ms = 0.0;
     bool tuned = false;
     hipGraphExec_t exec = nullptr;
@@ -139,8 +139,9 @@ ebic_status reserve(ebic_batch *b, int64_t n_cand, int64_t n_cols, int64_t n_mas
     return hgrow(b, b->h_cols, std::max<int64_t>(n_cols, 1), b->hcap_cols);
 }
 
-// Fills the run table for a request; returns the total number of tiles.
-uint64_t fill_runs(ebic_batch *b, const Request &q) {
+// Fills the run table for a request (tiles of 256 lanes with `words` 64-row
+// words each); returns the total number of tiles.
+uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words) {
     const int32_t R = (int32_t)b->ctx.size();
     int64_t cand = 0, maskw = 0;
     uint64_t tiles = 0;
@@ -150,7 +151,8 @@ uint64_t fill_runs(ebic_batch *b, const Request &q) {
         b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
                                 maskw};
         b->h_tile_base[r] = (uint32_t)tiles;
-        tiles += ((uint64_t)P * (uint64_t)c->W + 255) / 256;
+        const uint64_t items = (uint64_t)((c->W + words - 1) / words);
+        tiles += ((uint64_t)P * items + 255) / 256;
         cand += P;
         if (q.masks) maskw += (int64_t)P * 2 * c->W;
     }
@@ -158,7 +160,8 @@ uint64_t fill_runs(ebic_batch *b, const Request &q) {
     return tiles;
 }
 
-BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll) {
+BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
+                        int32_t words) {
     BatchLaunch L{};
     L.runs = b->d_runs;
     L.tile_base = b->d_tile_base;
@@ -179,6 +182,7 @@ BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int
     L.fitness = b->d_fit;
     L.grid = (uint32_t)workgroups;
     L.unroll = unroll;
+    L.words = words;
     return L;
 }
 
@@ -188,7 +192,7 @@ bool same_graph(const BatchLaunch &a, const BatchLaunch &x) {
            a.offsets == x.offsets && a.cols == x.cols && a.n_entries == x.n_entries &&
            a.sigma == x.sigma && a.k == x.k && a.negative == x.negative && a.masks == x.masks &&
            a.acc == x.acc && a.counts == x.counts && a.fitness == x.fitness && a.grid == x.grid &&
-           a.unroll == x.unroll;
+           a.unroll == x.unroll && a.words == x.words;
 }
 
 // Graph = [copy of the run table and tile bases (fixed size), kernel].
@@ -224,15 +228,15 @@ ebic_status launch_graph(ebic_batch *b, const BatchLaunch &L) {
 // Runs one packed request (CBF already in h_off/h_cols, P per run set).
 // Results land in h_counts/h_fit (and d_masks when asked).
 ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
-                        bool copy_back = true) {
-    const uint64_t tiles = fill_runs(b, q);
+                        int32_t words, bool copy_back = true) {
+    const uint64_t tiles = fill_runs(b, q, words);
     if (tiles == 0) return EBIC_OK;
     BHIP(hipMemcpyAsync(b->d_off, b->h_off, sizeof(int32_t) * (size_t)(q.n_cand + 1),
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipEventRecord(b->ev0, b->stream));
-    ebic_status st = launch_graph(b, make_launch(b, q, std::max(1, workgroups), unroll));
+    ebic_status st = launch_graph(b, make_launch(b, q, std::max(1, workgroups), unroll, words));
     if (st != EBIC_OK) return st;
     BHIP(hipEventRecord(b->ev1, b->stream));
     if (copy_back) {
@@ -252,24 +256,26 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
 // the fastest (median of a few replays each).  Shapes differ only in speed:
 // every shape computes the same results.
 ebic_status tune(ebic_batch *b, const Request &q) {
-    const uint64_t tiles = fill_runs(b, q);
+    const uint64_t tiles = fill_runs(b, q, 1);
     if (tiles == 0) return EBIC_OK;
     const int32_t full = b->resident_wgs;
     std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full,
                                   (int32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1),
                                                               (uint64_t)1 << 20)};
     const int32_t unrolls[] = {2, 4, 8};
+    const int32_t word_counts[] = {1, 2};
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     double best = 1e300;
-    int32_t best_g = full, best_u = 4;
+    int32_t best_g = full, best_u = 4, best_v = 1;
+    for (int32_t v : word_counts)
     for (int32_t u : unrolls)
         for (int32_t g : grids) {
             std::vector<float> t;
             for (int rep = 0; rep < 4; ++rep) {
                 BHIP(hipEventRecord(e0, b->stream));
-                ebic_status st = run_request(b, q, g, u, false);
+                ebic_status st = run_request(b, q, g, u, v, false);
                 if (st != EBIC_OK) return st;
                 BHIP(hipEventRecord(e1, b->stream));
                 BHIP(hipEventSynchronize(e1));
@@ -283,12 +289,14 @@ ebic_status tune(ebic_batch *b, const Request &q) {
                 best = med;
                 best_g = g;
                 best_u = u;
+                best_v = v;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->workgroups = best_g;
     b->unroll = best_u;
+    b->words = best_v;
     b->tuned_ms = best;
     b->tuned = true;
     return EBIC_OK;
@@ -407,16 +415,20 @@ ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
     t->workgroups = b->workgroups;
     t->unroll = b->unroll;
     t->best_ms = b->tuned ? b->tuned_ms : 0.0;
+    t->words_per_lane = b->words;
     return EBIC_OK;
 }
 
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t) {
     if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
         return bfail(EBIC_E_ARG, "null argument or struct_size too small");
-    if (t->workgroups < 0 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8))
-        return bfail(EBIC_E_ARG, "workgroups must be >= 0 and unroll 2, 4 or 8");
+    if (t->workgroups < 0 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8) ||
+        (t->words_per_lane != 1 && t->words_per_lane != 2))
+        return bfail(EBIC_E_ARG,
+                     "workgroups must be >= 0, unroll 2, 4 or 8 and words_per_lane 1 or 2");
     b->workgroups = t->workgroups ? t->workgroups : b->resident_wgs;
     b->unroll = t->unroll;
+    b->words = t->words_per_lane;
     b->tuned = true;
     b->tuned_ms = 0.0;
     return EBIC_OK;
@@ -468,7 +480,7 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
     for (int32_t r = 0; r < R; ++r)
         if (q.P[(size_t)r]) pk.add(offsets[r], cols[r], q.P[(size_t)r]);
     if (tune_now && (st = tune(b, q)) != EBIC_OK) return st;
-    if ((st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+    if ((st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
     int64_t cand = 0, mw = 0;
     for (int32_t r = 0; r < R; ++r) {
         const int32_t n = q.P[(size_t)r];
@@ -564,7 +576,7 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
         if (first && !b->tuned && (st = tune(b, q)) != EBIC_OK) return st;
         first = false;
         const auto e0 = std::chrono::steady_clock::now();
-        if ((st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+        if ((st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
         eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
         evaluated += q.n_cand;
         std::vector<int64_t> base((size_t)R + 1, 0);
@@ -599,7 +611,7 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
     for (int32_t r = 0; r < R; ++r)
         if (q.P[(size_t)r]) pk.add(tops[(size_t)r].off.data(), tops[(size_t)r].cols.data(), q.P[(size_t)r]);
     const auto e0 = std::chrono::steady_clock::now();
-    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll)) != EBIC_OK) return st;
+    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
     std::vector<uint64_t> all_masks((size_t)std::max<int64_t>(n_mask, 1));
     if (n_mask)
         BHIP(hipMemcpy(all_masks.data(), b->d_masks, sizeof(uint64_t) * (size_t)n_mask,

@@ -78,6 +78,7 @@ struct BatchLaunch {
     double *fitness;
     uint32_t grid;     // persistent workgroups
     int32_t unroll;    // pairs per batch of loads: 2, 4 or 8
+    int32_t words;     // 64-row words per lane: 1 or 2 (a tile is 256 lanes)
 };
 
 hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream);

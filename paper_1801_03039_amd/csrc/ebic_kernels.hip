@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
 // The last workgroup to leave resets the queue, so the launch can be
 // replayed (a captured graph) without any clearing step.  work[0] is the
 // next tile, work[1] the number of workgroups that have left.
-template <int K, bool NEG, int U>
+template <int K, bool NEG, int U, int V>
 __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
     const IndexRun *__restrict__ runs, const uint32_t *__restrict__ tile_base, int32_t n_runs,
     unsigned int *__restrict__ work, const int32_t *__restrict__ offsets,
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
         const uint32_t t = s_tile;
         if (t >= total_tiles) break;  // uniform
         const int32_t r = s_run;
-        index_tile<K, NEG, U, 1, false>(runs[r], t - tile_base[r], 0, offsets, cols, n_entries,
+        index_tile<K, NEG, U, V, false>(runs[r], t - tile_base[r], 0, offsets, cols, n_entries,
                                         sigma, masks, acc, counts, fitness);
     }
     if (threadIdx.x == 0) {
@@ -734,43 +734,53 @@ hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n,
     return hipGetLastError();
 }
 
-template <int K, int U>
+template <int K, int U, int V>
 static void launch_batch_k(const BatchLaunch &b, hipStream_t stream) {
     if (b.negative)
-        hipLaunchKernelGGL((eval_index_batch_kernel<K, true, U>), dim3(b.grid), dim3(kBlock), 0,
+        hipLaunchKernelGGL((eval_index_batch_kernel<K, true, U, V>), dim3(b.grid), dim3(kBlock), 0,
                            stream, b.runs, b.tile_base, b.n_runs, b.work, b.offsets, b.cols,
                            b.n_entries, b.sigma, b.masks, b.acc, b.counts, b.fitness);
     else
-        hipLaunchKernelGGL((eval_index_batch_kernel<K, false, U>), dim3(b.grid), dim3(kBlock), 0,
-                           stream, b.runs, b.tile_base, b.n_runs, b.work, b.offsets, b.cols,
+        hipLaunchKernelGGL((eval_index_batch_kernel<K, false, U, V>), dim3(b.grid), dim3(kBlock),
+                           0, stream, b.runs, b.tile_base, b.n_runs, b.work, b.offsets, b.cols,
                            b.n_entries, b.sigma, b.masks, b.acc, b.counts, b.fitness);
 }
 
-template <int U>
-static hipError_t launch_batch_u(const BatchLaunch &b, hipStream_t stream) {
+template <int U, int V>
+static hipError_t launch_batch_uv(const BatchLaunch &b, hipStream_t stream) {
     switch (b.k) {
-    case 0: launch_batch_k<0, U>(b, stream); break;
-    case 1: launch_batch_k<1, U>(b, stream); break;
-    case 2: launch_batch_k<2, U>(b, stream); break;
-    case 3: launch_batch_k<3, U>(b, stream); break;
+    case 0: launch_batch_k<0, U, V>(b, stream); break;
+    case 1: launch_batch_k<1, U, V>(b, stream); break;
+    case 2: launch_batch_k<2, U, V>(b, stream); break;
+    case 3: launch_batch_k<3, U, V>(b, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int V>
+static hipError_t launch_batch_v(const BatchLaunch &b, hipStream_t stream) {
+    switch (b.unroll) {
+    case 2: return launch_batch_uv<2, V>(b, stream);
+    case 4: return launch_batch_uv<4, V>(b, stream);
+    case 8: return launch_batch_uv<8, V>(b, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 int batch_wgs_per_cu() {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, eval_index_batch_kernel<1, true, 4>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks,
+                                                     eval_index_batch_kernel<1, true, 4, 1>,
                                                      kBlock, 0) != hipSuccess || blocks < 1)
         blocks = 1;
     return blocks;
 }
 
 hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream) {
-    switch (b.unroll) {
-    case 2: return launch_batch_u<2>(b, stream);
-    case 4: return launch_batch_u<4>(b, stream);
-    case 8: return launch_batch_u<8>(b, stream);
+    switch (b.words) {
+    case 1: return launch_batch_v<1>(b, stream);
+    case 2: return launch_batch_v<2>(b, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -78,6 +78,12 @@ __global__ __launch_bounds__(kBlock) void pool_fwd_kernel(const float *__restric
 //   dE[j] += dX[b][0:D] / L
 //   dF[j] += dX[b][D:2D] * T[next column] / (L-1)   (j not last)
 //   dT[j] += dX[b][D:2D] * F[previous column] / (L-1) (j not first)
+// Workgroup = (column j, slice of kLaneW embedding dims); its kRows rows of
+// lanes take occurrences r, r + kRows, ... in order, and row 0 adds the
+// rows' partial sums in row order.
+constexpr int kLaneW = 32;
+constexpr int kRows = kBlock / kLaneW;
+
 __global__ __launch_bounds__(kBlock) void pool_bwd_kernel(const float *__restrict__ dX, int32_t D,
                                                           const float *__restrict__ F,
                                                           const float *__restrict__ T,
@@ -89,40 +95,83 @@ __global__ __launch_bounds__(kBlock) void pool_bwd_kernel(const float *__restric
                                                           int32_t M, float *__restrict__ dE,
                                                           float *__restrict__ dF,
                                                           float *__restrict__ dT) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= (int64_t)M * D) return;
-    const int32_t j = (int32_t)(i / D), d = (int32_t)(i - (int64_t)j * D);
+    const int32_t j = blockIdx.x;
+    const int32_t r = threadIdx.x / kLaneW;
+    const int32_t d = blockIdx.y * kLaneW + (int32_t)(threadIdx.x % kLaneW);
     float ge = 0.f, gf = 0.f, gt = 0.f;
-    for (int32_t o = occ_start[j]; o < occ_start[j + 1]; ++o) {
-        const int32_t pos = occ_pos[o], b = occ_b[o];
-        const int32_t s = off[b], e = off[b + 1];
-        const float *dx = dX + (int64_t)b * 2 * D;
-        ge += dx[d] / (float)(e - s);
-        if (e - s > 1) {
-            const float inv = 1.f / (float)(e - s - 1);
-            if (pos + 1 < e) gf += dx[D + d] * T[(int64_t)cols[pos + 1] * D + d] * inv;
-            if (pos > s) gt += dx[D + d] * F[(int64_t)cols[pos - 1] * D + d] * inv;
+    if (d < D) {
+        const int32_t o1 = occ_start[j + 1];
+        for (int32_t o = occ_start[j] + r; o < o1; o += kRows) {
+            const int32_t pos = occ_pos[o], b = occ_b[o];
+            const int32_t s = off[b], e = off[b + 1];
+            const float *dx = dX + (int64_t)b * 2 * D;
+            ge += dx[d] / (float)(e - s);
+            if (e - s > 1) {
+                const float inv = 1.f / (float)(e - s - 1);
+                if (pos + 1 < e) gf += dx[D + d] * T[(int64_t)cols[pos + 1] * D + d] * inv;
+                if (pos > s) gt += dx[D + d] * F[(int64_t)cols[pos - 1] * D + d] * inv;
+            }
         }
     }
-    dE[i] = ge;
-    dF[i] = gf;
-    dT[i] = gt;
+    __shared__ float s_g[3][kRows][kLaneW];
+    const int32_t c = threadIdx.x % kLaneW;
+    s_g[0][r][c] = ge;
+    s_g[1][r][c] = gf;
+    s_g[2][r][c] = gt;
+    __syncthreads();
+    if (r == 0 && d < D) {
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        for (int32_t k = 0; k < kRows; ++k) {
+            a0 += s_g[0][k][c];
+            a1 += s_g[1][k][c];
+            a2 += s_g[2][k][c];
+        }
+        const int64_t i = (int64_t)j * D + d;
+        dE[i] = a0;
+        dF[i] = a1;
+        dT[i] = a2;
+    }
 }
 
 // Gradient of the length embedding: dZ[l] = sum of dX[b][0:D] over the
 // candidates of length l (len_b[len_start[l] .. len_start[l+1]), in
-// candidate order).
+// candidate order).  Workgroup = (length l, slice of kLaneW dims); rows of
+// lanes take list entries r, r + kRows, ... and row 0 adds the partial sums
+// in row order.
 __global__ __launch_bounds__(kBlock) void len_bwd_kernel(const float *__restrict__ dX, int32_t D,
                                                          const int32_t *__restrict__ len_start,
                                                          const int32_t *__restrict__ len_b,
                                                          int32_t n_len, float *__restrict__ dZl) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= (int64_t)n_len * D) return;
-    const int32_t l = (int32_t)(i / D), d = (int32_t)(i - (int64_t)l * D);
+    const int32_t l = blockIdx.x;
+    const int32_t r = threadIdx.x / kLaneW;
+    const int32_t c = threadIdx.x % kLaneW;
+    const int32_t d = blockIdx.y * kLaneW + c;
     float acc = 0.f;
-    for (int32_t o = len_start[l]; o < len_start[l + 1]; ++o)
-        acc += dX[(int64_t)len_b[o] * 2 * D + d];
-    dZl[i] = acc;
+    if (d < D) {
+        const int32_t o1 = len_start[l + 1];
+        int32_t o = len_start[l] + r;
+        // four entries per step: their indices, then their values, then the
+        // additions in list order
+        for (; o + 3 * kRows < o1; o += 4 * kRows) {
+            int32_t bb[4];
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bb[k] = len_b[o + k * kRows];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = dX[(int64_t)bb[k] * 2 * D + d];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += v[k];
+        }
+        for (; o < o1; o += kRows) acc += dX[(int64_t)len_b[o] * 2 * D + d];
+    }
+    __shared__ float s_p[kRows][kLaneW];
+    s_p[r][c] = acc;
+    __syncthreads();
+    if (r == 0 && d < D) {
+        float a = 0.f;
+        for (int32_t k = 0; k < kRows; ++k) a += s_p[k][c];
+        dZl[(int64_t)l * D + d] = a;
+    }
 }
 
 // ----------------------------------------------------------------- GEMM --
@@ -252,7 +301,15 @@ __global__ __launch_bounds__(kBlock) void colsum_kernel(const float *__restrict_
     const int32_t chunk = (B + splits - 1) / splits;
     const int32_t b0 = s * chunk, b1 = b0 + chunk < B ? b0 + chunk : B;
     float acc = 0.f;
-    for (int32_t b = b0; b < b1; ++b) acc += (w ? w[b] : 1.f) * X[(int64_t)b * N + n];
+    int32_t b = b0;
+    for (; b + 7 < b1; b += 8) {   // eight loads in flight, additions in row order
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (w ? w[b + k] : 1.f) * X[(int64_t)(b + k) * N + n];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; b < b1; ++b) acc += (w ? w[b] : 1.f) * X[(int64_t)b * N + n];
     ws[(int64_t)s * N + n] = acc;
 }
 
@@ -326,7 +383,15 @@ __global__ __launch_bounds__(kBlock) void dw3_kernel(const uint16_t *__restrict_
     const int32_t chunk = (B + splits - 1) / splits;
     const int32_t b0 = s * chunk, b1 = b0 + chunk < B ? b0 + chunk : B;
     float acc = 0.f;
-    for (int32_t b = b0; b < b1; ++b) acc += dy[b] * from_bf16(H2b[(int64_t)b * N + n]);
+    int32_t b = b0;
+    for (; b + 7 < b1; b += 8) {   // eight loads in flight, additions in row order
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = dy[b + k] * from_bf16(H2b[(int64_t)(b + k) * N + n]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; b < b1; ++b) acc += dy[b] * from_bf16(H2b[(int64_t)b * N + n]);
     ws[(int64_t)s * N + n] = acc;
 }
 
@@ -370,8 +435,9 @@ hipError_t pool_fwd(const float *E, const float *F, const float *T, const float 
 
 hipError_t len_bwd(const float *dX, int32_t D, const int32_t *len_start, const int32_t *len_b,
                    int32_t n_len, float *dZl, hipStream_t s) {
-    hipLaunchKernelGGL(len_bwd_kernel, grid1((int64_t)n_len * D), dim3(kBlock), 0, s, dX, D,
-                       len_start, len_b, n_len, dZl);
+    const dim3 grid((unsigned)n_len, (unsigned)((D + kLaneW - 1) / kLaneW));
+    hipLaunchKernelGGL(len_bwd_kernel, grid, dim3(kBlock), 0, s, dX, D, len_start, len_b, n_len,
+                       dZl);
     return hipGetLastError();
 }
 
@@ -379,8 +445,9 @@ hipError_t pool_bwd(const float *dX, int32_t D, const float *F, const float *T, 
                     const int32_t *cols, const int32_t *occ_start, const int32_t *occ_pos,
                     const int32_t *occ_b, int32_t M, float *dE, float *dF, float *dT,
                     hipStream_t s) {
-    hipLaunchKernelGGL(pool_bwd_kernel, grid1((int64_t)M * D), dim3(kBlock), 0, s, dX, D, F, T,
-                       off, cols, occ_start, occ_pos, occ_b, M, dE, dF, dT);
+    const dim3 grid((unsigned)M, (unsigned)((D + kLaneW - 1) / kLaneW));
+    hipLaunchKernelGGL(pool_bwd_kernel, grid, dim3(kBlock), 0, s, dX, D, F, T, off, cols,
+                       occ_start, occ_pos, occ_b, M, dE, dF, dT);
     return hipGetLastError();
 }
 

@@ -103,16 +103,20 @@ def test_every_launch_shape_agrees(E, mats):
                          tune=True)
         t = b.tuning()
         assert t["unroll"] in (2, 4, 8) and t["workgroups"] >= 1 and t["best_ms"] > 0
+        assert t["words_per_lane"] in (1, 2)
         _check_runs(mats, pops, ref, 5, 2, True)
         for wg in (1, 0, 7, 5000):
             for u in (2, 4, 8):
-                _note(f"shape wg={wg} unroll={u}")
-                b.set_tuning(wg, u)
-                got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
-                                 want_masks=True)
-                for g, r in zip(got, ref):
-                    assert np.array_equal(g["counts"], r["counts"])
-                    assert np.array_equal(g["masks"], r["masks"])
+                for v in (1, 2):
+                    _note(f"shape wg={wg} unroll={u} words={v}")
+                    b.set_tuning(wg, u, v)
+                    got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
+                                     want_masks=True)
+                    for g, r in zip(got, ref):
+                        assert np.array_equal(g["counts"], r["counts"])
+                        assert np.array_equal(g["fitness"].view(np.int64),
+                                              r["fitness"].view(np.int64))
+                        assert np.array_equal(g["masks"], r["masks"])
 
 
 def test_batch_errors(E, mats):
