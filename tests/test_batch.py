@@ -76,6 +76,27 @@ def test_batch_evaluate_matches_oracle(E, mats):
                 _check_runs(mats, pops, got, 6, k, neg)
 
 
+def test_full_batched_configuration(E):
+    # The batched workload at full size: 64 runs on matrices of uneven shapes
+    # (rows log-uniform 500-50000, columns 20-1000), a full mixed population
+    # of 1024 per run, tuned launch shape; every run against the oracle.
+    ws = [synth.batched_workload(r) for r in range(64)]
+    data = [synth.make_matrix(w) for w in ws]
+    rng = np.random.default_rng(1000)
+    pops = [synth.pack_cbf(synth.mixed_population(rng, w, pl, w.population))
+            for w, (a, pl) in zip(ws, data)]
+    with E.Batch([a for a, _ in data]) as b:
+        _note("full batched configuration, tuned")
+        got = b.evaluate(pops, sigma=25, tune=True)
+        _note(f"tuning {b.tuning()}")
+        got2 = b.evaluate(pops, sigma=25)
+    for w, (a, _), pop, g, g2 in zip(ws, data, pops, got, got2):
+        ref = oracle.evaluate(a, pop[0], pop[1], sigma=25)
+        assert np.array_equal(g["counts"], ref["counts"]), w.name
+        assert np.array_equal(g["fitness"].view(np.int64), ref["fitness"].view(np.int64))
+        assert np.array_equal(g2["counts"], ref["counts"])
+
+
 def test_graph_replays_interleaved_with_eager_work(E, mats):
     # The captured graph is replayed with a new run table each time, with
     # eager single-context work and host synchronisation in between; every

@@ -128,7 +128,7 @@ def test_workload_populations(ebic, name, path):
     _check(ebic, a, pop, path, sigma=w.sigma, k=w.max_violations, neg=w.negative_trends)
 
 
-@pytest.mark.parametrize("name", ["expression", "wide"])
+@pytest.mark.parametrize("name", ["expression", "wide", "surrogate"])
 def test_full_size_device_entry_point(ebic, name):
     """Full workload size, full population, through the device entry point
     with torch tensors on the current stream, both paths; compared with the
