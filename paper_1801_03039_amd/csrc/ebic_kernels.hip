@@ -409,10 +409,17 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
     const bool span_ok = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
     const bool lane_ok = !ok_range || (start >= b0 && end <= b1);
     const bool use_lds = __syncthreads_and(span_ok && lane_ok) != 0;
+    // Staging also checks every staged column: when none is out of range
+    // (the common case) the per-candidate validation below is skipped.
+    bool staged_bad = true;
     if (use_lds) {
-        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += (int32_t)blockDim.x)
-            s_cols[e] = cols[b0 + e];
-        __syncthreads();
+        bool inval = false;
+        for (int32_t e = tid; e < (int32_t)(b1 - b0); e += (int32_t)blockDim.x) {
+            const int32_t x = cols[b0 + e];
+            inval |= x < 0 || x >= m;
+            s_cols[e] = x;
+        }
+        staged_bad = __syncthreads_or(inval) != 0;
     }
     const int32_t lds0 = (int32_t)(start - b0);
 
@@ -438,10 +445,11 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
             else return cols[start + t];
         };
         // The lane of the first word validates every column (batched,
-        // branch-free reads) and reports the verdict with its part; other
-        // lanes only clamp column indices so that no read leaves the index.
-        if (active && g == 0) {
-            bad = !ok_range;
+        // branch-free reads; skipped when staging found every staged column
+        // in range) and reports the verdict with its part; other lanes only
+        // clamp column indices so that no read leaves the index.
+        if (active && g == 0) bad = !ok_range;
+        if (active && g == 0 && (!kLds || staged_bad)) {
             for (int32_t t = 0; t < L; t += U) {
                 int32_t x[U];
 #pragma unroll
