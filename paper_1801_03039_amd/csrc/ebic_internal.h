@@ -94,8 +94,12 @@ bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               const EvalArgs &e, hipStream_t stream);
 
-hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
-                             int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream);
+// `ties`: some column pair of the matrix has a tied or unordered row (any
+// tie flag set); when false the falling test never reads flags or reverse
+// words.
+hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, bool ties, int64_t n,
+                             int32_t m, int64_t W, int64_t wpad, const EvalArgs &e,
+                             hipStream_t stream);
 
 }  // namespace ebic
 
@@ -109,6 +113,7 @@ struct ebic_ctx {
     // pairwise order index
     uint64_t *d_idx = nullptr;
     uint8_t *d_tie = nullptr;    // m*m tie flags of the index
+    bool any_tie = true;         // some tie flag is set (known once the index is built)
     int64_t idx_bytes = 0;
     int64_t idx_budget = 0;
     bool idx_built = false;

@@ -352,7 +352,7 @@ __device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)
 //     ceil(W / V) <= kBlock); counts are summed with LDS atomics and the
 //     first lane of each candidate writes its result after a workgroup
 //     barrier -- no global atomics and no accumulator scratch.
-template <int K, bool NEG, int U, int V, bool ALIGNED>
+template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES = true, bool OFF32 = false>
 __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uint32_t cpw,
                                            const int32_t *__restrict__ offsets,
                                            const int32_t *__restrict__ cols, int64_t n_entries,
@@ -459,7 +459,18 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
             }
         }
         if (!any_valid) return;
-        const auto base = idx + w0;
+        // Address of the words of pair row `pq`: with OFF32 (index < 4 GiB)
+        // a 32-bit byte offset from the uniform base, which the compiler
+        // forms as a scalar base plus one offset register per load.
+        auto words_at = [&](int64_t pq) {
+            if constexpr (OFF32) {
+                typedef const __attribute__((address_space(1))) char *gchar;
+                const uint32_t off = ((uint32_t)pq * (uint32_t)wpad + (uint32_t)w0) * 8u;
+                return (global_ptr<uint64_t>)((gchar)idx + off);
+            } else {
+                return idx + w0 + pq * wpad;
+            }
+        };
         const int32_t last = L - 1;
         int32_t p = col(0);
         p = (p < 0 || p >= m) ? 0 : p;
@@ -479,8 +490,8 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t pq = (int64_t)pp * m + q[u];
-                load_words<V>(base + pq * wpad, lu[u]);
-                if (NEG) tf[u] = tie[pq];
+                load_words<V>(words_at(pq), lu[u]);
+                if (NEG) tf[u] = TIES ? tie[pq] : 0;
                 pp = q[u];
             }
 #pragma unroll
@@ -496,8 +507,8 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                 pp = p;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (tf[u]) {
-                        load_words<V>(base + ((int64_t)q[u] * m + pp) * wpad, ld[u]);
+                    if (TIES && tf[u]) {
+                        load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
                     } else {
 #pragma unroll
                         for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
@@ -572,14 +583,14 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                     counts, fitness);
 }
 
-template <int K, bool NEG, int U, int V, bool ALIGNED>
+template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES, bool OFF32>
 __global__ __launch_bounds__(kBlock) void eval_index_kernel(
     IndexRun R, uint32_t cpw, const int32_t *__restrict__ offsets,
     const int32_t *__restrict__ cols, int64_t n_entries, int32_t sigma,
     uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
     int32_t *__restrict__ counts, double *__restrict__ fitness) {
-    index_tile<K, NEG, U, V, ALIGNED>(R, blockIdx.x, cpw, offsets, cols, n_entries, sigma, masks,
-                                      acc, counts, fitness);
+    index_tile<K, NEG, U, V, ALIGNED, TIES, OFF32>(R, blockIdx.x, cpw, offsets, cols, n_entries,
+                                                   sigma, masks, acc, counts, fitness);
 }
 
 // --------------------------------------------------- batched (many runs) --
@@ -686,26 +697,45 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
     return hipGetLastError();
 }
 
+// Falling trends read tie flags (and reverse words) only when the matrix
+// has a tied or unordered pair somewhere (`ties`); otherwise lt(q,p) is
+// ~lt(p,q) for every pair and the flags are not loaded.
+template <int K, int U, int V, bool ALIGNED, bool OFF32>
+static void launch_index_o(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 block,
+                           const EvalArgs &e, bool ties, hipStream_t stream) {
+    if (e.negative && ties)
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, true, OFF32>), grid, block,
+                           0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
+                           e.acc, e.counts, e.fitness);
+    else if (e.negative)
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, false, OFF32>), grid, block,
+                           0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
+                           e.acc, e.counts, e.fitness);
+    else
+        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V, ALIGNED, false, OFF32>), grid, block,
+                           0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
+                           e.acc, e.counts, e.fitness);
+}
+
+// 32-bit index offsets when the whole index is below 4 GiB.
 template <int K, int U, int V, bool ALIGNED>
 static void launch_index_t(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 block,
-                           const EvalArgs &e, hipStream_t stream) {
-    if (e.negative)
-        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED>), grid, block, 0, stream, R,
-                           cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc, e.counts,
-                           e.fitness);
+                           const EvalArgs &e, bool ties, hipStream_t stream) {
+    const uint64_t bytes = (uint64_t)R.m * (uint64_t)R.m * (uint64_t)R.wpad * 8ull;
+    if (bytes <= 0xFFFFFFFFull)
+        launch_index_o<K, U, V, ALIGNED, true>(R, cpw, grid, block, e, ties, stream);
     else
-        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V, ALIGNED>), grid, block, 0, stream,
-                           R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks, e.acc,
-                           e.counts, e.fitness);
+        launch_index_o<K, U, V, ALIGNED, false>(R, cpw, grid, block, e, ties, stream);
 }
 
 template <int K, int U, int V>
-static void launch_aligned(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
+static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
     const int64_t Wg = (R.W + V - 1) / V;
     const int64_t cpw = kBlock / Wg;
     const int64_t threads = (cpw * Wg + kWave - 1) / kWave * kWave;
     const dim3 grid((unsigned)((R.P + cpw - 1) / cpw));
-    launch_index_t<K, U, V, true>(R, (uint32_t)cpw, grid, dim3((unsigned)threads), e, stream);
+    launch_index_t<K, U, V, true>(R, (uint32_t)cpw, grid, dim3((unsigned)threads), e, ties,
+                                  stream);
 }
 
 // Tiling by matrix height.  Up to 1024 words (65536 rows) a workgroup holds
@@ -714,29 +744,30 @@ static void launch_aligned(const IndexRun &R, const EvalArgs &e, hipStream_t str
 // a workgroup just large enough (whole waves) to hold them.  Taller
 // matrices use the flattened tiling with 2 words per lane.
 template <int K, int U>
-static void launch_index_k(const IndexRun &R, const EvalArgs &e, hipStream_t stream) {
+static void launch_index_k(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
     if (R.W <= kBlock)
-        launch_aligned<K, U, 1>(R, e, stream);
+        launch_aligned<K, U, 1>(R, e, ties, stream);
     else if (R.W <= 2 * kBlock)
-        launch_aligned<K, U, 2>(R, e, stream);
+        launch_aligned<K, U, 2>(R, e, ties, stream);
     else if (R.W <= 4 * kBlock)
-        launch_aligned<K, U, 4>(R, e, stream);
+        launch_aligned<K, U, 4>(R, e, ties, stream);
     else {
         constexpr int V = kWordsPerLane;
         const int64_t total = (int64_t)R.P * ((R.W + V - 1) / V);
         const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
-        launch_index_t<K, U, V, false>(R, 0, grid, dim3(kBlock), e, stream);
+        launch_index_t<K, U, V, false>(R, 0, grid, dim3(kBlock), e, ties, stream);
     }
 }
 
-hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, int64_t n, int32_t m,
-                             int64_t W, int64_t wpad, const EvalArgs &e, hipStream_t stream) {
+hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, bool ties, int64_t n,
+                             int32_t m, int64_t W, int64_t wpad, const EvalArgs &e,
+                             hipStream_t stream) {
     const IndexRun R{idx, tie, e.logt, n, W, wpad, m, e.P, 0, 0};
     switch (e.k) {
-    case 0: launch_index_k<0, kUnroll>(R, e, stream); break;
-    case 1: launch_index_k<1, kUnroll>(R, e, stream); break;
-    case 2: launch_index_k<2, kUnroll>(R, e, stream); break;
-    case 3: launch_index_k<3, kUnroll>(R, e, stream); break;
+    case 0: launch_index_k<0, kUnroll>(R, e, ties, stream); break;
+    case 1: launch_index_k<1, kUnroll>(R, e, ties, stream); break;
+    case 2: launch_index_k<2, kUnroll>(R, e, ties, stream); break;
+    case 3: launch_index_k<3, kUnroll>(R, e, ties, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

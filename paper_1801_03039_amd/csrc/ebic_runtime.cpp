@@ -111,6 +111,10 @@ ebic_status build_index(ebic_ctx *ctx) {
     HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // Whether any pair has a tied or unordered row (m*m bytes, once).
+    std::vector<uint8_t> flags((size_t)ctx->m * (size_t)ctx->m);
+    HIP_TRY(ctx, hipMemcpy(flags.data(), ctx->d_tie, flags.size(), hipMemcpyDeviceToHost));
+    ctx->any_tie = std::any_of(flags.begin(), flags.end(), [](uint8_t f) { return f != 0; });
     ctx->idx_ms = ms;
     ctx->idx_built = true;
     return EBIC_OK;
@@ -148,8 +152,8 @@ ebic_status launch_all(ebic_ctx *ctx, const EvalArgs &e, bool use_index, hipStre
     if (items > kMaxLaunchThreads)
         return fail(ctx, EBIC_E_ARG, "population too large for one launch; split it");
     if (use_index)
-        HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->d_tie, ctx->n, ctx->m, ctx->W, ctx->wpad,
-                                       e, s));
+        HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->d_tie, ctx->any_tie, ctx->n, ctx->m,
+                                       ctx->W, ctx->wpad, e, s));
     else
         HIP_TRY(ctx, launch_eval_direct(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, e, s));
     return EBIC_OK;
