@@ -118,7 +118,7 @@ def tie_pairs(a, series):
     return out
 
 
-def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks, ties=None):
+def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks, ties=None, any_tie=True):
     """Bytes each evaluator must move, from the oracle's exact per-row
     decision depths d(c, r) (values read before row r's decision is fixed).
 
@@ -126,9 +126,9 @@ def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks, ties=None):
     index (word-level):  per (candidate, 64-row word), for each of the first
                          k_w = max_{r in w} (d - 1) pairs (until every row of
                          the word is decided): the 8-byte order word lt(p,q),
-                         plus, with falling trends on, the 8-byte word lt(q,p)
-                         when the pair has a tie and a 1-byte tie flag per
-                         (candidate, pair)
+                         plus, with falling trends on a matrix that has tied
+                         pairs (any_tie), the 8-byte word lt(q,p) when the pair
+                         has a tie and a 1-byte tie flag per (candidate, pair)
     both add the CBF (4 (P + 1 + sum L)) and outputs (4P + 8P, + 16 P W masks)."""
     W = (n + 63) // 64
     io = 4 * (P + 1 + sum_L) + 12 * P + (16 * P * W if want_masks else 0)
@@ -137,7 +137,7 @@ def algorithmic_bytes(depth, n, P, sum_L, negative, want_masks, ties=None):
     pad[:, :n] = depth
     pairs = np.clip(pad.reshape(P, W, 64).max(axis=2).astype(np.int64) - 1, 0, None)  # [P, W]
     b_idx = 8 * int(pairs.sum()) + io
-    if negative:
+    if negative and any_tie:     # without tied pairs the flags are never needed
         for c in range(P):
             t = ties[c]
             if t.size and t.any():
@@ -525,7 +525,9 @@ def main():
         }
         out["vs_plain"] = round(value / out["cpu_baseline"]["value"], 1)
         ties = tie_pairs(a, pop) if (use_index and w.negative_trends) else None
-        b_seq, b_idx = algorithmic_bytes(ref["depth"], N, P, sum_L, w.negative_trends, False, ties)
+        any_tie = bool(ctx.info()["index_ties"])
+        b_seq, b_idx = algorithmic_bytes(ref["depth"], N, P, sum_L, w.negative_trends, False, ties,
+                                         any_tie)
         b_alg = b_idx if use_index else b_seq
         achieved = b_alg / (kern_ms * 1e-3) / 1e9
         out["roofline"] = {
@@ -536,8 +538,9 @@ def main():
             "kernel": "eval_index_kernel" if use_index else "eval_direct_kernel",
             "bytes_per_launch": b_alg,
             "bytes_rule": ("8 B order word per (candidate, 64-row word, pair) until the word is "
-                           "decided, +8 B reverse word on tie pairs and a 1 B tie flag per "
-                           "(candidate, pair) when falling trends are on; plus CBF and outputs"
+                           "decided; with falling trends on a matrix with tied pairs, +8 B "
+                           "reverse word on tie pairs and a 1 B tie flag per (candidate, pair); "
+                           "plus CBF and outputs"
                            if use_index else "4 B per FP32 value a row must read until decided; "
                            "plus CBF and outputs"),
         }

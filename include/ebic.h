@@ -87,6 +87,8 @@ typedef struct {
     int64_t index_bytes;      /* size of the index (built or prospective) */
     int64_t index_budget;     /* AUTO builds the index only within this many bytes */
     double index_build_ms;    /* device time of the last index build */
+    int32_t index_ties;       /* 1 if some column pair has a tied or unordered row (then
+                                 the falling test reads tie flags); valid once built */
 } ebic_ctx_info;
 
 /*

@@ -57,7 +57,7 @@ class CtxInfo(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("device", _i32), ("n_rows", _i64), ("n_cols", _i32),
                 ("rows_padded", _i64), ("mask_words", _i64), ("path", _i32),
                 ("index_built", _i32), ("index_bytes", _i64), ("index_budget", _i64),
-                ("index_build_ms", _dbl)]
+                ("index_build_ms", _dbl), ("index_ties", _i32)]
 
 
 GENERATION_FN = ctypes.CFUNCTYPE(None, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),

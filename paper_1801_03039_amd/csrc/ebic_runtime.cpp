@@ -332,6 +332,7 @@ ebic_status ebic_get_info(const ebic_ctx *ctx, ebic_ctx_info *info) {
     info->index_bytes = ctx->idx_bytes;
     info->index_budget = ctx->idx_budget;
     info->index_build_ms = ctx->idx_ms;
+    info->index_ties = ctx->any_tie ? 1 : 0;
     return EBIC_OK;
 }
 
