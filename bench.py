@@ -303,20 +303,11 @@ def run_surrogate(args):
         info = []
         rs, ts, ws_ = timed(lambda **kw: ebic.evolve_surrogate(ctx, seed, G, cfg,
                                                                on_surrogate=info.append, **kw))
-        # Reference: the same screening with exact fitness as the ranking
-        # (GPU evaluations through the Python binding).
-        def ev(o, c, sigma, k, neg, want_masks):
-            r = ctx.evaluate(o, c, sigma=sigma, max_violations=k, negative_trends=neg,
-                             want_masks=want_masks)
-            return r["counts"], r["fitness"], r.get("masks")
-
-        def exact_score(o, c):
-            return ctx.evaluate(o, c, sigma=w.sigma, max_violations=w.max_violations,
-                                negative_trends=w.negative_trends)["fitness"]
+        # Reference: the same screening with the pool ranked by its exact
+        # fitness, evaluated on the GPU (ebic_evolve_oversampled).
         log(f"surrogate bench: exact-ranked screen seed {seed}")
-        rx, tx, wx = timed(lambda **kw: ebic.evolve_screened_with(
-            ev, exact_score, w.n_rows, w.n_cols, seed, G, cfg, oversample=8,
-            warmup_generations=3, **kw))
+        rx, tx, wx = timed(lambda **kw: ebic.evolve_oversampled(ctx, seed, G, cfg, oversample=8,
+                                                                warmup_generations=3, **kw))
         f_star = max(f for _, f in tp)
         t_exact = first_reach(tx, f_star)
         rec_x, rel_x = recovery_vs_planted(ebic, rx, planted, w.n_rows, dev)
@@ -342,8 +333,27 @@ def run_surrogate(args):
             "speedup_at_f_star": None if t_sur is None else round(t_plain / t_sur, 3),
         })
         log(json.dumps(runs[-1]))
+    # Cost of ranking one pool (8 x 1536 children of the last plain
+    # generation's shape) by the network vs by exact evaluation.
+    rng = np.random.default_rng(99)
+    pool = synth.random_population(rng, w.n_cols, 8 * 1536, w.len_min, w.len_max)
+    p_off, p_cols = synth.pack_cbf(pool)
+    with ebic.Mlp(w.n_cols, seed=1) as net:
+        net.predict(p_off, p_cols)
+        t0 = time.perf_counter()
+        for _ in range(10):
+            net.predict(p_off, p_cols)
+        t_mlp = (time.perf_counter() - t0) / 10
+    kw_e = dict(sigma=w.sigma, max_violations=w.max_violations, negative_trends=w.negative_trends)
+    ctx.evaluate(p_off, p_cols, **kw_e)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        ctx.evaluate(p_off, p_cols, **kw_e)
+    t_exact = (time.perf_counter() - t0) / 10
     ctx.close()
     sp = [r["speedup_at_f_star"] for r in runs]
+    sx = [r["plain"]["t_f_star_s"] / r["exact_ranked_screen"]["t_f_star_s"] for r in runs
+          if r["exact_ranked_screen"]["t_f_star_s"]]
     out = {
         "metric": "surrogate speedup at equal fitness",
         "value": None if any(x is None for x in sp) else round(float(np.exp(np.mean(np.log(sp)))), 3),
@@ -355,6 +365,11 @@ def run_surrogate(args):
                                f"k={w.max_violations}, rising+falling, sigma={w.sigma}, G={G}",
                    "seeds": seeds},
         "runs": runs,
+        "exact_ranked_screen_speedup_at_f_star": (
+            round(float(np.exp(np.mean(np.log(sx)))), 3) if len(sx) == len(runs) else None),
+        "pool_ranking_ms": {"pool": len(pool), "mlp_predict": round(t_mlp * 1e3, 3),
+                            "exact_evaluate": round(t_exact * 1e3, 3),
+                            "rows_at_equal_cost_if_linear_in_rows": int(w.n_rows * t_mlp / t_exact)},
     }
     print(json.dumps(out), flush=True)
 

@@ -276,6 +276,18 @@ ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_user, ebic_s
                                       int32_t warmup_generations, int32_t host_threads,
                                       const ebic_evolve_params *params, ebic_result **out);
 
+/*
+ * Offspring screening by exact fitness on the GPU (not in the paper): the
+ * screened run of ebic_evolve_screened_with, with the pool of oversample x
+ * (P - elites) children ranked by its exact Eq. (1) fitness (params->eval),
+ * evaluated on ctx like any population.  The kept children's scores are
+ * those exact values.  stats.candidates_evaluated and eval_ms include the
+ * pools.  Errors as ebic_evolve.
+ */
+ebic_status ebic_evolve_oversampled(ebic_ctx *ctx, uint64_t seed, int32_t generations,
+                                    int32_t oversample, int32_t warmup_generations,
+                                    const ebic_evolve_params *params, ebic_result **out);
+
 /* Result of a run: the top-rank biclusters after Step 7, best first. */
 typedef struct {
     uint32_t struct_size;       /* sizeof(ebic_run_stats) */

@@ -501,6 +501,27 @@ def evolve_screened_with(evaluate: Callable, score: Callable, n_rows: int, n_col
     return _finish(res, n_rows)
 
 
+_evolve_oversampled = _sig("ebic_evolve_oversampled", _i32,
+                           [_vp, _u64, _i32, _i32, _i32, _P(EvolveParamsC), _P(_vp)])
+EXPORTED += ["ebic_evolve_oversampled"]
+
+
+def evolve_oversampled(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
+                       oversample: int = 8, warmup_generations: int = 3,
+                       on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
+    """Offspring screening by exact GPU fitness (``ebic_evolve_oversampled``)."""
+    cb = _gen_callback(on_generation)
+    p = _params_c(cfg, cb)
+    res = _vp()
+    st = _evolve_oversampled(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations),
+                             int(oversample), int(warmup_generations), ctypes.byref(p),
+                             ctypes.byref(res))
+    if st != EBIC_OK:
+        msg = _last_error(ctx.handle).decode(errors="replace") or _last_error(None).decode(errors="replace")
+        raise EbicError(st, msg)
+    return _finish(res, ctx.n_rows)
+
+
 # -------------------------------------------------------------- batched runs --
 
 class BatchTuning(ctypes.Structure):

@@ -101,25 +101,20 @@ ebic_status run(Evaluator &ev, int64_t n_rows, int32_t M, uint64_t seed, int32_t
     return EBIC_OK;
 }
 
-// Screened run with a caller-supplied scorer (the host side of the
-// surrogate-screened run, with any ranking).  Generations after `warmup`
-// draw an oversampled pool and keep the children `score` ranks highest.
-ebic_status run_screened(Evaluator &ev, ebic_score_fn score, void *score_user, int64_t n_rows,
-                         int32_t M, uint64_t seed, int32_t generations, int32_t oversample,
-                         int32_t warmup, int32_t threads, const ebic_evolve_params &p,
-                         ebic_result **out) {
+// Screened run (offspring screening; not in the paper).  Generations after
+// `warmup` draw an oversampled pool and keep the children `scorer` ranks
+// highest; `scorer(pool, &status)` returns one float or double per child.
+template <typename Scorer>
+ebic_status run_screened(Evaluator &ev, Scorer &&score_pool, int64_t n_rows, int32_t M,
+                         uint64_t seed, int32_t generations, int32_t oversample, int32_t warmup,
+                         int32_t threads, const ebic_evolve_params &p, ebic_result **out) {
     const auto t_start = Clock::now();
     const int64_t W = (n_rows + 63) / 64;
     Run run(M, seed, generations, p);
     std::vector<int32_t> cnt, po;
     std::vector<double> fit;
     ebic_status score_st = EBIC_OK;
-    auto scorer = [&](const Pop &pool) {
-        std::vector<float> sc((size_t)pool.size(), -INFINITY);
-        ebic_status e = score(score_user, pool.off.data(), pool.cols.data(), pool.size(), sc.data());
-        if (e != EBIC_OK) score_st = e;
-        return sc;
-    };
+    auto scorer = [&](const Pop &pool) { return score_pool(pool, &score_st); };
     for (;;) {
         const bool screen = run.generation() > warmup;
         const bool more = screen ? run.next_screened(oversample, scorer, threads) : run.next();
@@ -255,6 +250,48 @@ extern "C" ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_u
     if (st != EBIC_OK) return st;
     *out = nullptr;
     Evaluator ev{eval, eval_user};
-    return run_screened(ev, score, score_user, n_rows, n_cols, seed, generations, oversample,
+    auto scorer = [&](const Pop &pool, ebic_status *st) {
+        std::vector<float> sc((size_t)pool.size(), -INFINITY);
+        ebic_status e = score(score_user, pool.off.data(), pool.cols.data(), pool.size(), sc.data());
+        if (e != EBIC_OK) *st = e;
+        return sc;
+    };
+    return run_screened(ev, scorer, n_rows, n_cols, seed, generations, oversample,
                         warmup_generations, host_threads, *params, out);
+}
+
+extern "C" ebic_status ebic_evolve_oversampled(ebic_ctx *ctx, uint64_t seed, int32_t generations,
+                                               int32_t oversample, int32_t warmup_generations,
+                                               const ebic_evolve_params *params,
+                                               ebic_result **out) {
+    if (!ctx || !out) return evolve_error(EBIC_E_ARG, "ctx and out must not be null");
+    if (generations < 0 || oversample < 1 || warmup_generations < 0)
+        return evolve_error(EBIC_E_ARG, "need generations >= 0, oversample >= 1, warmup >= 0");
+    ebic_ctx_info info{};
+    info.struct_size = sizeof(info);
+    ebic_status st = ebic_get_info(ctx, &info);
+    if (st != EBIC_OK) return st;
+    if ((st = check_params(params, info.n_rows, info.n_cols)) != EBIC_OK) return st;
+    *out = nullptr;
+    Evaluator ev{ctx_eval, ctx};
+    // The pool is ranked by its exact fitness (evaluation-time parameters),
+    // evaluated on the GPU like any population.
+    ebic_params ep = params->eval;
+    ep.want_masks = 0;
+    std::vector<int32_t> cnt;
+    auto scorer = [&](const Pop &pool, ebic_status *sst) {
+        std::vector<double> sc((size_t)pool.size(), -INFINITY);
+        cnt.resize((size_t)pool.size());
+        const auto t0 = Clock::now();
+        ebic_status e = pool.size() > 0
+                            ? ebic_evaluate(ctx, pool.off.data(), pool.cols.data(), pool.size(),
+                                            &ep, nullptr, cnt.data(), sc.data())
+                            : EBIC_OK;
+        ev.ms += ms_since(t0);
+        ev.evaluated += pool.size();
+        if (e != EBIC_OK) *sst = e;
+        return sc;
+    };
+    return run_screened(ev, scorer, info.n_rows, info.n_cols, seed, generations, oversample,
+                        warmup_generations, 0, *params, out);
 }

@@ -622,7 +622,7 @@ class Run {
             stopped_ = true;
             return false;
         }
-        std::vector<float> sc = score(pool_);
+        auto sc = score(pool_);      // one float or double per pooled child
         std::vector<int32_t> order((size_t)pool_.size());
         for (int32_t i = 0; i < pool_.size(); ++i) {
             order[(size_t)i] = i;
