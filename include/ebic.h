@@ -306,6 +306,58 @@ ebic_status ebic_result_stats(const ebic_result *r, ebic_run_stats *stats);
 void ebic_result_free(ebic_result *r);
 
 /*
+ * Stateful runs and checkpoints.  An ebic_run is the run of ebic_evolve
+ * (same draws, same result) advanced a few generations at a time; between
+ * generations it can be saved to bytes and resumed from them, and the
+ * resumed run continues exactly as the uninterrupted one would (the random
+ * stream, the last scored population, the tabu list and the top-rank list
+ * are saved; caches are rebuilt).  ebic_run_create evaluates on ctx;
+ * ebic_run_create_with on a caller's evaluator (as ebic_evolve_with).
+ * Generation 0 is Step 1; ebic_run_advance performs up to max_generations
+ * more generations (each: build, evaluate, Step 5) and sets *finished when
+ * the run is over (all generations done or stopped by the tabu rule).
+ * params is copied; its on_generation is called as in ebic_evolve (its
+ * `user` must stay valid while the run advances).  ebic_run_result performs Steps 6-7 on the current top-rank list
+ * (the run may still be advanced afterwards).
+ *
+ * Checkpoint bytes (ebic_run_save: with buf NULL only *size is set; E_RANGE
+ * when capacity < *size): a magic tag, a version, the matrix shape, the
+ * generation count, the draw-deciding parameters, then the run state.
+ * ebic_run_load refuses (E_ARG) bytes of another matrix shape, other
+ * parameters, another version, or bytes that do not parse.  Timing and
+ * evaluation counters restart at zero in a loaded run.  Errors: message via
+ * ebic_last_error(NULL) (evaluation failures: on ctx).
+ */
+typedef struct ebic_run ebic_run;
+typedef struct {
+    uint32_t struct_size;         /* sizeof(ebic_run_progress) */
+    int32_t next_generation;      /* index of the next generation to build */
+    int32_t generations_run;      /* generations completed after Step 1 */
+    int32_t stopped_by_tabu;
+    int32_t toplist;              /* entries in the top-rank list */
+    double best_fitness;          /* fitness of its first entry (0 if empty) */
+    int64_t tabu_size;            /* distinct series seen */
+    int64_t candidates_evaluated; /* since creation or load */
+    double eval_ms, wall_ms;      /* since creation or load */
+} ebic_run_progress;
+
+ebic_status ebic_run_create(ebic_ctx *ctx, uint64_t seed, int32_t generations,
+                            const ebic_evolve_params *params, ebic_run **out);
+ebic_status ebic_run_create_with(ebic_eval_fn eval, void *eval_user, int64_t n_rows,
+                                 int32_t n_cols, uint64_t seed, int32_t generations,
+                                 const ebic_evolve_params *params, ebic_run **out);
+ebic_status ebic_run_advance(ebic_run *r, int32_t max_generations, int32_t *finished);
+ebic_status ebic_run_get_progress(const ebic_run *r, ebic_run_progress *out);
+ebic_status ebic_run_save(const ebic_run *r, void *buf, int64_t capacity, int64_t *size);
+ebic_status ebic_run_load(ebic_ctx *ctx, const ebic_evolve_params *params, const void *buf,
+                          int64_t size, ebic_run **out);
+ebic_status ebic_run_load_with(ebic_eval_fn eval, void *eval_user, int64_t n_rows,
+                               int32_t n_cols, const ebic_evolve_params *params, const void *buf,
+                               int64_t size, ebic_run **out);
+ebic_status ebic_run_result(ebic_run *r, ebic_result **out);
+void ebic_run_destroy(ebic_run *r);
+
+/*
  * Batched EBIC: many independent runs, each on its own matrix (any shapes),
  * sharing one GPU launch per generation.  Each run behaves exactly as
  * ebic_evolve on its own context with its own seed; the runs' populations

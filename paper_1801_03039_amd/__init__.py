@@ -14,7 +14,7 @@ CPU fallback: using them without a built library raises ``ImportError``.
 """
 _EXPORTS = (
     "Batch", "Context", "EbicError", "EBIC_PATH_AUTO", "EBIC_PATH_DIRECT", "EBIC_PATH_INDEX",
-    "LIB_PATH", "EvolveConfig", "EvolveResult", "Generation", "Mlp", "Trend", "evolve",
+    "LIB_PATH", "EvolveConfig", "EvolveResult", "Generation", "Mlp", "Run", "Trend", "evolve",
     "evolve_surrogate", "evolve_screened_with", "evolve_oversampled", "evolve_with", "make_params", "mask_words", "mask_rows",
     "match_scores", "binding",
 )

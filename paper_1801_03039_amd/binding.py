@@ -522,6 +522,137 @@ def evolve_oversampled(ctx: Context, seed: int, generations: int, cfg: EvolveCon
     return _finish(res, ctx.n_rows)
 
 
+class RunProgressC(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("next_generation", _i32), ("generations_run", _i32),
+                ("stopped_by_tabu", _i32), ("toplist", _i32), ("best_fitness", _dbl),
+                ("tabu_size", _i64), ("candidates_evaluated", _i64), ("eval_ms", _dbl),
+                ("wall_ms", _dbl)]
+
+
+_run_create = _sig("ebic_run_create", _i32, [_vp, _u64, _i32, _P(EvolveParamsC), _P(_vp)])
+_run_create_with = _sig("ebic_run_create_with", _i32,
+                        [EVAL_FN, _vp, _i64, _i32, _u64, _i32, _P(EvolveParamsC), _P(_vp)])
+_run_advance = _sig("ebic_run_advance", _i32, [_vp, _i32, _P(_i32)])
+_run_get_progress = _sig("ebic_run_get_progress", _i32, [_vp, _P(RunProgressC)])
+_run_save = _sig("ebic_run_save", _i32, [_vp, _vp, _i64, _P(_i64)])
+_run_load = _sig("ebic_run_load", _i32, [_vp, _P(EvolveParamsC), _vp, _i64, _P(_vp)])
+_run_load_with = _sig("ebic_run_load_with", _i32,
+                      [EVAL_FN, _vp, _i64, _i32, _P(EvolveParamsC), _vp, _i64, _P(_vp)])
+_run_result = _sig("ebic_run_result", _i32, [_vp, _P(_vp)])
+_run_destroy = _sig("ebic_run_destroy", None, [_vp])
+EXPORTED += ["ebic_run_create", "ebic_run_create_with", "ebic_run_advance",
+             "ebic_run_get_progress", "ebic_run_save", "ebic_run_load", "ebic_run_load_with",
+             "ebic_run_result", "ebic_run_destroy"]
+
+
+def _eval_callback(evaluate: Callable, n_rows: int, errors: list):
+    W = mask_words(n_rows)
+
+    def cb(user, off, cols, P, prm, masks, counts, fit):
+        try:
+            o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
+            n = int(o[-1])
+            c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
+            pr = prm.contents
+            cnt, f, m = evaluate(o, c, pr.sigma, pr.max_violations, bool(pr.negative_trends),
+                                 bool(pr.want_masks))
+            np.ctypeslib.as_array(counts, shape=(P,))[:] = cnt
+            np.ctypeslib.as_array(fit, shape=(P,))[:] = f
+            if pr.want_masks:
+                np.ctypeslib.as_array(masks, shape=(P * 2 * W,))[:] = np.asarray(m, dtype=np.uint64).ravel()
+            return EBIC_OK
+        except Exception as ex:  # reported by the caller
+            errors.append(ex)
+            return EBIC_E_DEVICE
+    return EVAL_FN(cb)
+
+
+class Run:
+    """A stateful EBIC run (``ebic_run_*``): advance, checkpoint, resume.
+
+    ``Run(cfg, seed, generations, ctx=ctx)`` evaluates on a GPU context;
+    ``Run(cfg, seed, generations, evaluate=fn, n_rows=N, n_cols=M)`` on a
+    Python evaluator (as ``evolve_with``).  ``Run.load(cfg, data, ...)``
+    resumes from ``save()`` bytes."""
+
+    def __init__(self, cfg: EvolveConfig, seed: int = 0, generations: int = 0, *, ctx=None,
+                 evaluate: Optional[Callable] = None, n_rows: int = 0, n_cols: int = 0,
+                 on_generation: Optional[Callable[[Generation], None]] = None, _data=None):
+        self._errors = []
+        self._gcb = _gen_callback(on_generation)
+        self._p = _params_c(cfg, self._gcb)
+        self._ctx = ctx
+        self.n_rows = ctx.n_rows if ctx is not None else int(n_rows)
+        h = _vp()
+        if ctx is not None:
+            st = (_run_create(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations),
+                              ctypes.byref(self._p), ctypes.byref(h)) if _data is None else
+                  _run_load(ctx.handle, ctypes.byref(self._p), _data, len(_data), ctypes.byref(h)))
+        else:
+            self._efn = _eval_callback(evaluate, n_rows, self._errors)
+            st = (_run_create_with(self._efn, None, int(n_rows), int(n_cols),
+                                   int(seed) & ((1 << 64) - 1), int(generations),
+                                   ctypes.byref(self._p), ctypes.byref(h)) if _data is None else
+                  _run_load_with(self._efn, None, int(n_rows), int(n_cols), ctypes.byref(self._p),
+                                 _data, len(_data), ctypes.byref(h)))
+        self._raise(st)
+        self._h = h
+
+    @classmethod
+    def load(cls, cfg: EvolveConfig, data: bytes, **kw) -> "Run":
+        return cls(cfg, _data=bytes(data), **kw)
+
+    def _raise(self, st):
+        if self._errors:
+            raise self._errors.pop(0)
+        if st != EBIC_OK:
+            msg = _last_error(None).decode(errors="replace")
+            if self._ctx is not None and not msg:
+                msg = _last_error(self._ctx.handle).decode(errors="replace")
+            raise EbicError(st, msg)
+
+    def advance(self, generations: int) -> bool:
+        """Run up to ``generations`` more generations; True when the run is over."""
+        fin = _i32()
+        self._raise(_run_advance(self._h, int(generations), ctypes.byref(fin)))
+        return bool(fin.value)
+
+    def progress(self) -> dict:
+        pr = RunProgressC()
+        pr.struct_size = ctypes.sizeof(RunProgressC)
+        self._raise(_run_get_progress(self._h, ctypes.byref(pr)))
+        return {f: getattr(pr, f) for f, _ in RunProgressC._fields_ if f != "struct_size"}
+
+    def save(self) -> bytes:
+        n = _i64()
+        self._raise(_run_save(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._raise(_run_save(self._h, buf, n.value, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def result(self) -> EvolveResult:
+        res = _vp()
+        self._raise(_run_result(self._h, ctypes.byref(res)))
+        return _finish(res, self.n_rows)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _run_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 # -------------------------------------------------------------- batched runs --
 
 class BatchTuning(ctypes.Structure):

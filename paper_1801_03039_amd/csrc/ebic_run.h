@@ -53,6 +53,52 @@ struct SplitMix64 {
     uint32_t below(uint64_t n) { return (uint32_t)(next() % n); }
 };
 
+// Checkpoint bytes: little-endian PODs and vectors (length first).
+struct Writer {
+    std::vector<uint8_t> &b;
+    template <typename T>
+    void put(const T &v) {
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+    }
+    template <typename T>
+    void vec(const std::vector<T> &v) {
+        put<uint64_t>(v.size());
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(v.data());
+        b.insert(b.end(), p, p + sizeof(T) * v.size());
+    }
+};
+
+struct Reader {
+    const uint8_t *p;
+    size_t n, at = 0;
+    bool ok = true;
+    template <typename T>
+    T get() {
+        T v{};
+        if (!ok || n - at < sizeof(T)) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, p + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    template <typename T>
+    std::vector<T> vec(size_t max_elems) {
+        const uint64_t k = get<uint64_t>();
+        std::vector<T> v;
+        if (!ok || k > max_elems || (n - at) / sizeof(T) < k) {
+            ok = false;
+            return v;
+        }
+        v.resize((size_t)k);
+        std::memcpy(v.data(), p + at, sizeof(T) * (size_t)k);
+        at += sizeof(T) * (size_t)k;
+        return v;
+    }
+};
+
 // A population in CBF form.
 struct Pop {
     std::vector<int32_t> off{0};
@@ -71,6 +117,27 @@ struct Pop {
     void push(const int32_t *s, int32_t L) {
         cols.insert(cols.end(), s, s + L);
         off.push_back((int32_t)cols.size());
+    }
+    void save(Writer &w) const {
+        w.vec(off);
+        w.vec(cols);
+        w.vec(counts);
+        w.vec(fit);
+    }
+    // Loads and checks the CBF shape (offsets from 0, increasing, columns
+    // in [0, M), scores for every member).
+    bool load(Reader &r, int32_t M) {
+        const size_t cap = (size_t)1 << 31;
+        off = r.vec<int32_t>(cap);
+        cols = r.vec<int32_t>(cap);
+        counts = r.vec<int32_t>(cap);
+        fit = r.vec<double>(cap);
+        if (!r.ok || off.empty() || off[0] != 0 || (size_t)off.back() != cols.size()) return false;
+        for (size_t i = 1; i < off.size(); ++i)
+            if (off[i] <= off[i - 1]) return false;
+        for (int32_t c : cols)
+            if (c < 0 || c >= M) return false;
+        return counts.size() == off.size() - 1 && fit.size() == counts.size();
     }
 };
 
@@ -96,6 +163,34 @@ class Tabu {
         arena_.insert(arena_.end(), s, s + L);
         ++used_;
         return true;
+    }
+
+    size_t size() const { return used_; }
+    // The set as its series in insertion order (the arena and each entry's
+    // length); loading re-inserts them.
+    void save(Writer &w) const {
+        std::vector<int32_t> lens(used_);
+        std::vector<std::pair<size_t, int32_t>> at;
+        at.reserve(used_);
+        for (const Slot &e : slots_)
+            if (e.len >= 0) at.emplace_back(e.at, e.len);
+        std::sort(at.begin(), at.end());
+        for (size_t i = 0; i < at.size(); ++i) lens[i] = at[i].second;
+        w.vec(arena_);
+        w.vec(lens);
+    }
+    bool load(Reader &r) {
+        const std::vector<int32_t> arena = r.vec<int32_t>((size_t)1 << 40);
+        const std::vector<int32_t> lens = r.vec<int32_t>((size_t)1 << 40);
+        if (!r.ok) return false;
+        *this = Tabu();
+        size_t at = 0;
+        for (int32_t L : lens) {
+            if (L < 1 || arena.size() - at < (size_t)L) return false;
+            if (!insert(arena.data() + at, L)) return false;
+            at += (size_t)L;
+        }
+        return at == arena.size();
     }
 
   private:
@@ -249,6 +344,31 @@ class TopRank {
         std::stable_sort(top_.begin(), top_.end(),
                          [](const TopEntry &a, const TopEntry &b) { return a.fit > b.fit; });
         if ((int32_t)top_.size() > K) top_.resize((size_t)K);
+    }
+
+    void save(Writer &w) const {
+        w.put<uint64_t>(top_.size());
+        for (const TopEntry &e : top_) {
+            w.vec(e.s);
+            w.put(e.count);
+            w.put(e.fit);
+        }
+    }
+    bool load(Reader &r, int32_t M) {
+        const uint64_t k = r.get<uint64_t>();
+        if (!r.ok || k > ((uint64_t)1 << 31)) return false;
+        top_.clear();
+        for (uint64_t i = 0; i < k; ++i) {
+            TopEntry e;
+            e.s = r.vec<int32_t>((size_t)M);
+            e.count = r.get<int32_t>();
+            e.fit = r.get<double>();
+            if (!r.ok || e.s.empty()) return false;
+            for (int32_t c : e.s)
+                if (c < 0 || c >= M) return false;
+            top_.push_back(std::move(e));
+        }
+        return true;
     }
 
   private:
@@ -485,6 +605,33 @@ class Run {
     const std::vector<TopEntry> &top() const { return toprank_.entries(); }
     int32_t generations_run() const { return gens_run_; }
     bool stopped() const { return stopped_; }
+    size_t tabu_size() const { return tabu_.size(); }
+    int32_t generations() const { return generations_; }
+
+    // Checkpoint of the run between generations (after accept()): the
+    // random stream, counters, the last scored population, the tabu list and
+    // the top-rank list.  The parameters are the caller's to supply again.
+    void save(Writer &w) const {
+        w.put(br_.rng.s);
+        w.put(gen_);
+        w.put(first_);
+        w.put(gens_run_);
+        w.put<uint8_t>(stopped_ ? 1 : 0);
+        prev_.save(w);
+        tabu_.save(w);
+        toprank_.save(w);
+    }
+    bool load(Reader &r) {
+        br_.rng.s = r.get<uint64_t>();
+        gen_ = r.get<int32_t>();
+        first_ = r.get<int32_t>();
+        gens_run_ = r.get<int32_t>();
+        stopped_ = r.get<uint8_t>() != 0;
+        if (!r.ok || gen_ < 0 || gens_run_ < 0 || first_ < 0) return false;
+        if (!prev_.load(r, M_) || !tabu_.load(r) || !toprank_.load(r, M_)) return false;
+        cur_.clear();
+        return gen_ == 0 || prev_.size() > 0;
+    }
 
   private:
     // Step 1: P distinct random series.

@@ -69,3 +69,31 @@ def test_workload_first_generations(E, name, gens):
     a, _ = synth.make_matrix(w)
     _note(f"{name} first {gens} generations")
     _run_both(E, a, w, w.seed, gens, "auto")
+
+
+def test_checkpointed_gpu_run_equals_evolve(E):
+    # a GPU run saved after a few generations and resumed on a fresh
+    # context equals the uninterrupted ebic_evolve run
+    w = synth.WORKLOADS["expression"]
+    a, _ = synth.make_matrix(w)
+    cfg = E.EvolveConfig(population=512, len_min=w.len_min, len_max=w.len_max,
+                            eval=E.Trend(w.sigma, w.max_violations, w.negative_trends),
+                            expand=E.Trend(w.sigma, w.max_violations, True))
+    ref_gens, gens = [], []
+    with E.Context(a) as ctx:
+        _note("checkpoint: uninterrupted run")
+        ref = E.evolve(ctx, 21, 10, cfg, on_generation=ref_gens.append)
+        with E.Run(cfg, 21, 10, ctx=ctx, on_generation=gens.append) as run:
+            run.advance(4)
+            data = run.save()
+    with E.Context(a) as ctx2:
+        _note("checkpoint: resumed run")
+        with E.Run.load(cfg, data, ctx=ctx2, on_generation=gens.append) as run:
+            assert run.advance(100)
+            res = run.result()
+    assert [g.population for g in gens] == [g.population for g in ref_gens]
+    for g, h in zip(gens, ref_gens):
+        assert np.array_equal(g.fitness.view(np.int64), h.fitness.view(np.int64))
+    assert [b["cols"] for b in res.biclusters] == [b["cols"] for b in ref.biclusters]
+    for b, c in zip(res.biclusters, ref.biclusters):
+        assert np.array_equal(b["mask_words"], c["mask_words"])
