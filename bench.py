@@ -238,6 +238,22 @@ def run_batched(args):
         out["cpu_baseline"] = {"value": round(n_checks / tc / 1e9, 4), "unit": "Gtrend-checks/s",
                                "cores": cores, "kind": "oracle",
                                "sample": f"runs {sample} (their full populations)"}
+        # Algorithmic bytes of one launch: every run's exact decision depths.
+        log("batched: algorithmic bytes from the oracle's decision depths")
+        b_alg = 0
+        for i, w in enumerate(ws):
+            off_i, cols_i = pops[i]
+            d = oracle.evaluate(data[i][0], off_i, cols_i, sigma=25, want_depth=True,
+                                nthreads=cores)["depth"]
+            b_alg += algorithmic_bytes(d, w.n_rows, len(off_i) - 1, int(off_i[-1]), False,
+                                       False)[1]
+            del d
+        achieved = b_alg / (dev_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": "eval_index_batch_kernel",
+                           "bytes_per_launch": b_alg,
+                           "duration": "device time of the launch graph (run-table copy + kernel)"}
     b.close()
     print(json.dumps(out), flush=True)
 
@@ -344,6 +360,19 @@ def run_surrogate(args):
         for _ in range(10):
             net.predict(p_off, p_cols)
         t_mlp = (time.perf_counter() - t0) / 10
+        # Training step of the replay batch size (4 generations of 2048):
+        # its dense products are the network's MFMA work.
+        tb = synth.random_population(rng, w.n_cols, 4 * 2048, w.len_min, w.len_max)
+        t_off, t_cols = synth.pack_cbf(tb)
+        target = rng.standard_normal(len(tb)).astype(np.float32)
+        net.train(t_off, t_cols, target, 2)
+        n_steps = 20
+        t0 = time.perf_counter()
+        net.train(t_off, t_cols, target, n_steps)
+        t_step = (time.perf_counter() - t0) / n_steps
+        D, H, B = net.embed_dim, net.hidden, len(tb)
+        # forward 2B(2D H + H H + H); backward twice that (data and weight grads)
+        flops = 3 * 2 * B * (2 * D * H + H * H + H)
     kw_e = dict(sigma=w.sigma, max_violations=w.max_violations, negative_trends=w.negative_trends)
     ctx.evaluate(p_off, p_cols, **kw_e)
     t0 = time.perf_counter()
@@ -351,6 +380,22 @@ def run_surrogate(args):
         ctx.evaluate(p_off, p_cols, **kw_e)
     t_exact = (time.perf_counter() - t0) / 10
     ctx.close()
+    cpu = None
+    if not args.no_cpu:
+        # the float64 oracle network's gradient on a bounded sample
+        from oracle import mlp as omlp
+        Bs = 512
+        o_s = np.asarray(t_off[:Bs + 1])
+        c_s = np.asarray(t_cols[:o_s[-1]])
+        params = np.random.default_rng(5).standard_normal(omlp.n_params(w.n_cols, D, H)) * 0.05
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):           # one core, BLAS included
+            t0 = time.perf_counter()
+            omlp.loss_and_grad(params, o_s, c_s, target[:Bs], w.n_cols, D, H, bf16=False)
+            t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(t_cpu * B / Bs * 1e3, 1), "unit": f"ms per training step (B={B})",
+               "cores": 1, "kind": "oracle",
+               "sample": f"float64 gradient of {Bs} series, scaled to {B}"}
     sp = [r["speedup_at_f_star"] for r in runs]
     sx = [r["plain"]["t_f_star_s"] / r["exact_ranked_screen"]["t_f_star_s"] for r in runs
           if r["exact_ranked_screen"]["t_f_star_s"]]
@@ -367,6 +412,13 @@ def run_surrogate(args):
         "runs": runs,
         "exact_ranked_screen_speedup_at_f_star": (
             round(float(np.exp(np.mean(np.log(sx)))), 3) if len(sx) == len(runs) else None),
+        "roofline": {"bound": "mfma", "achieved": round(flops / t_step / 1e12, 3),
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(flops / t_step / 1e12 / 2500.0, 5), "traffic": None,
+                     "kernel": "MLP training step (gemm_bf16_kernel and its companions)",
+                     "flops_per_step": flops, "ms_per_step": round(t_step * 1e3, 3),
+                     "batch": B},
+        "cpu_baseline": cpu,
         "pool_ranking_ms": {"pool": len(pool), "mlp_predict": round(t_mlp * 1e3, 3),
                             "exact_evaluate": round(t_exact * 1e3, 3),
                             "rows_at_equal_cost_if_linear_in_rows": int(w.n_rows * t_mlp / t_exact)},
