@@ -602,6 +602,9 @@ __global__ __launch_bounds__(kBlock) void eval_index_kernel(
 // The last workgroup to leave resets the queue, so the launch can be
 // replayed (a captured graph) without any clearing step.  work[0] is the
 // next tile, work[1] the number of workgroups that have left.
+constexpr int kRunsLds = 1024;   // tile bases kept in LDS (more runs: read from memory)
+static_assert(sizeof(IndexRun) % 8 == 0, "run descriptor copied as 8-byte words");
+
 template <int K, bool NEG, int U, int V>
 __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
     const IndexRun *__restrict__ runs, const uint32_t *__restrict__ tile_base, int32_t n_runs,
@@ -609,22 +612,34 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
     const int32_t *__restrict__ cols, int64_t n_entries, int32_t sigma,
     uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
     int32_t *__restrict__ counts, double *__restrict__ fitness) {
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tb[kRunsLds + 1];
+    __shared__ IndexRun s_R;
+    __shared__ uint32_t s_tile, s_local;
     __shared__ int32_t s_run;
+    const int tid = threadIdx.x;
+    const bool tb_lds = n_runs <= kRunsLds;
+    if (tb_lds)
+        for (int32_t i = tid; i <= n_runs; i += kBlock) s_tb[i] = tile_base[i];
     const uint32_t total_tiles = tile_base[n_runs];
+    // Thread 0 claims the next tile one iteration ahead, so the queue's
+    // atomic round trip overlaps the current tile's work.
+    uint32_t next = 0;
+    if (tid == 0) next = atomicAdd(work, 1u);
+    __syncthreads();  // s_tb filled
     for (;;) {
-        __syncthreads();  // the previous tile is finished by every wave
-        if (threadIdx.x == 0) {
-            const uint32_t t = atomicAdd(work, 1u);
+        if (tid == 0) {
+            const uint32_t t = next;
             int32_t r = 0;
             if (t < total_tiles) {
                 // last run whose first tile is <= t
                 int32_t lo = 0, hi = n_runs - 1;
                 while (lo < hi) {
                     const int32_t mid = (lo + hi + 1) >> 1;
-                    if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+                    const uint32_t base = tb_lds ? s_tb[mid] : tile_base[mid];
+                    if (base <= t) lo = mid; else hi = mid - 1;
                 }
                 r = lo;
+                s_local = t - (tb_lds ? s_tb[r] : tile_base[r]);
             }
             s_tile = t;
             s_run = r;
@@ -632,11 +647,18 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
         __syncthreads();
         const uint32_t t = s_tile;
         if (t >= total_tiles) break;  // uniform
-        const int32_t r = s_run;
-        index_tile<K, NEG, U, V, false>(runs[r], t - tile_base[r], 0, offsets, cols, n_entries,
-                                        sigma, masks, acc, counts, fitness);
+        // the tile's run descriptor into LDS, one 8-byte word per thread
+        constexpr int kWords = (int)(sizeof(IndexRun) / 8);
+        if (tid < kWords)
+            reinterpret_cast<uint64_t *>(&s_R)[tid] =
+                reinterpret_cast<const uint64_t *>(runs + s_run)[tid];
+        if (tid == 0) next = atomicAdd(work, 1u);
+        __syncthreads();
+        index_tile<K, NEG, U, V, false>(s_R, s_local, 0, offsets, cols, n_entries, sigma, masks,
+                                        acc, counts, fitness);
+        __syncthreads();  // every wave is done with s_R, s_local and s_cols
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         const unsigned left = atomicAdd(work + 1, 1u);
         if (left == gridDim.x - 1) {
             atomicExch(work, 0u);
