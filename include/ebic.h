@@ -376,8 +376,9 @@ ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, cons
                               const int32_t *n_cols, int32_t device, ebic_batch **out);
 ebic_status ebic_batch_destroy(ebic_batch *b);
 
-/* Launch shape of the persistent kernel: `workgroups` persistent
- * workgroups (0: one per resident slot), `unroll` pairs per batch of loads
+/* Launch shape of the batched kernel: `workgroups` persistent workgroups
+ * draining the tile queue (0: one per resident slot; -1: one workgroup per
+ * tile and no queue), `unroll` pairs per batch of loads
  * (2, 4 or 8) and `words_per_lane` 64-row words per lane (1 or 2; a tile is
  * 256 lanes, so 256 or 512 (candidate, word) pairs). */
 typedef struct {

@@ -49,6 +49,7 @@ struct ebic_batch {
     // launch shape and its graph
     int32_t resident_wgs = 0;       // workgroups resident at once (occupancy x CUs)
     int32_t workgroups = 0, unroll = 4, words = 1;
+    uint64_t static_grid = 0;   // grid of the queue-free mode (largest tile count so far)
     double tuned_ms = 0.0;
     bool tuned = false;
     hipGraphExec_t exec = nullptr;
@@ -160,13 +161,16 @@ uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words) {
     return tiles;
 }
 
+// workgroups < 0: one workgroup per tile, no queue; the grid is the largest
+// tile count seen so far (the kernel reads the current count), so that the
+// captured graph stays valid from one generation to the next.
 BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
-                        int32_t words) {
+                        int32_t words, uint64_t tiles) {
     BatchLaunch L{};
     L.runs = b->d_runs;
     L.tile_base = b->d_tile_base;
     L.n_runs = (int32_t)b->ctx.size();
-    L.work = b->d_work;
+    L.work = workgroups < 0 ? nullptr : b->d_work;
     L.offsets = b->d_off;
     L.cols = b->d_cols;
     // Bound for offsets checks: the allocated column buffer (stable across
@@ -180,7 +184,12 @@ BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int
     L.acc = b->d_acc;
     L.counts = b->d_counts;
     L.fitness = b->d_fit;
-    L.grid = (uint32_t)workgroups;
+    if (workgroups < 0) {
+        b->static_grid = std::max<uint64_t>(b->static_grid, tiles);
+        L.grid = (uint32_t)b->static_grid;
+    } else {
+        L.grid = (uint32_t)workgroups;
+    }
     L.unroll = unroll;
     L.words = words;
     return L;
@@ -236,7 +245,8 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
     BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipEventRecord(b->ev0, b->stream));
-    ebic_status st = launch_graph(b, make_launch(b, q, std::max(1, workgroups), unroll, words));
+    ebic_status st = launch_graph(
+        b, make_launch(b, q, workgroups < 0 ? -1 : std::max(1, workgroups), unroll, words, tiles));
     if (st != EBIC_OK) return st;
     BHIP(hipEventRecord(b->ev1, b->stream));
     if (copy_back) {
@@ -259,9 +269,8 @@ ebic_status tune(ebic_batch *b, const Request &q) {
     const uint64_t tiles = fill_runs(b, q, 1);
     if (tiles == 0) return EBIC_OK;
     const int32_t full = b->resident_wgs;
-    std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full,
-                                  (int32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1),
-                                                              (uint64_t)1 << 20)};
+    // persistent grids, and one workgroup per tile without a queue (-1)
+    std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full, -1};
     const int32_t unrolls[] = {2, 4, 8};
     const int32_t word_counts[] = {1, 2};
     hipEvent_t e0, e1;
@@ -422,10 +431,10 @@ ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t) {
     if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
         return bfail(EBIC_E_ARG, "null argument or struct_size too small");
-    if (t->workgroups < 0 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8) ||
+    if (t->workgroups < -1 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8) ||
         (t->words_per_lane != 1 && t->words_per_lane != 2))
         return bfail(EBIC_E_ARG,
-                     "workgroups must be >= 0, unroll 2, 4 or 8 and words_per_lane 1 or 2");
+                     "workgroups must be >= -1, unroll 2, 4 or 8 and words_per_lane 1 or 2");
     b->workgroups = t->workgroups ? t->workgroups : b->resident_wgs;
     b->unroll = t->unroll;
     b->words = t->words_per_lane;

@@ -76,10 +76,11 @@ struct BatchLaunch {
     unsigned long long *acc;
     int32_t *counts;
     double *fitness;
-    uint32_t grid;     // persistent workgroups
+    uint32_t grid;     // persistent workgroups, or the tile count when work is null
     int32_t unroll;    // pairs per batch of loads: 2, 4 or 8
     int32_t words;     // 64-row words per lane: 1 or 2 (a tile is 256 lanes)
 };
+// work == nullptr selects one tile per workgroup (no queue, grid = tiles).
 
 hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream);
 // Workgroups of the batch kernel resident per compute unit.

@@ -621,6 +621,22 @@ __global__ __launch_bounds__(kBlock) void eval_index_batch_kernel(
     if (tb_lds)
         for (int32_t i = tid; i <= n_runs; i += kBlock) s_tb[i] = tile_base[i];
     const uint32_t total_tiles = tile_base[n_runs];
+    if (work == nullptr) {
+        // One tile per workgroup (grid = total tiles): no queue.
+        __syncthreads();  // s_tb filled
+        const uint32_t t = blockIdx.x;
+        if (t >= total_tiles) return;  // uniform
+        int32_t lo = 0, hi = n_runs - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            const uint32_t base = tb_lds ? s_tb[mid] : tile_base[mid];
+            if (base <= t) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = t - (tb_lds ? s_tb[lo] : tile_base[lo]);
+        index_tile<K, NEG, U, V, false>(runs[lo], local, 0, offsets, cols, n_entries, sigma, masks,
+                                        acc, counts, fitness);
+        return;
+    }
     // Thread 0 claims the next tile one iteration ahead, so the queue's
     // atomic round trip overlaps the current tile's work.
     uint32_t next = 0;

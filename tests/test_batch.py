@@ -123,10 +123,11 @@ def test_every_launch_shape_agrees(E, mats):
         ref = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True, want_masks=True,
                          tune=True)
         t = b.tuning()
-        assert t["unroll"] in (2, 4, 8) and t["workgroups"] >= 1 and t["best_ms"] > 0
+        assert t["unroll"] in (2, 4, 8) and (t["workgroups"] >= 1 or t["workgroups"] == -1)
+        assert t["best_ms"] > 0
         assert t["words_per_lane"] in (1, 2)
         _check_runs(mats, pops, ref, 5, 2, True)
-        for wg in (1, 0, 7, 5000):
+        for wg in (1, 0, 7, 5000, -1):
             for u in (2, 4, 8):
                 for v in (1, 2):
                     _note(f"shape wg={wg} unroll={u} words={v}")
