@@ -490,11 +490,14 @@ ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *c
  * Every kept child is scored exactly on the GPU; only kept children enter
  * the tabu list.  The model is trained each generation (train_steps Adam
  * steps) on the exact (candidate, log(1 + fitness)) pairs of the last
- * replay_generations generations.  Before each generation is scored, the
- * model's predictions for its new members are compared with their exact
- * fitness (Spearman rank correlation); a generation is screened only if the
- * previous generation's correlation reached min_rank_corr, otherwise it is
- * bred exactly as in ebic_evolve (the plain method is the fallback).
+ * replay_generations generations.  The judge of the ranking: in a screened
+ * generation, judge_sample pool members drawn uniformly (from a stream of
+ * the judge's own) are also scored exactly and compared with the model's
+ * predictions (Spearman rank correlation); in a plainly bred generation the
+ * new members are.  A generation is screened only if the previous
+ * generation's correlation reached min_rank_corr, otherwise it is bred
+ * exactly as in ebic_evolve (the plain method is the fallback).  The
+ * sample's evaluations count in the run's statistics.
  * on_surrogate (may be NULL) reports, per generation: whether it was
  * screened, the rank correlation, the training loss and the pool size.
  */
@@ -506,11 +509,14 @@ typedef struct {
     int32_t warmup_generations;   /* 3 */
     int32_t train_steps;          /* 16 */
     int32_t replay_generations;   /* 4 */
-    double min_rank_corr;         /* 0.0 */
+    double min_rank_corr;         /* 0.1 */
     uint64_t mlp_seed;
     ebic_mlp_config mlp;          /* ebic_mlp_defaults with lr 3e-3 */
     ebic_surrogate_fn on_surrogate;
     void *user;
+    int32_t judge_sample;         /* 512: pool members scored exactly to judge the ranking */
+    int32_t exact_rerank;         /* 0; r > 0: the network keeps r x (P - elites) of the
+                                     pool, those are scored exactly and the best kept */
 } ebic_surrogate_params;
 
 void ebic_surrogate_defaults(ebic_surrogate_params *s);

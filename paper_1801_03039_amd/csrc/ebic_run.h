@@ -585,6 +585,11 @@ class Run {
     }
     const Pop &pending() const { return cur_; }
     int32_t first_new() const { return first_; }
+    // Elites the next Steps 2-3 will carry over: min(|top|, P * num / den).
+    int32_t elites() const {
+        return (int32_t)std::min<int64_t>((int64_t)toprank_.entries().size(),
+                                          (int64_t)p_.population * p_.elite_num / p_.elite_den);
+    }
     int32_t generation() const { return gen_; }
     const ebic_params &eval_params() const { return evalp_; }
     // Scores of members [first_new(), P) of pending().

@@ -78,7 +78,9 @@ void ebic_surrogate_defaults(ebic_surrogate_params *s) {
     s->warmup_generations = 3;
     s->train_steps = 16;
     s->replay_generations = 4;
-    s->min_rank_corr = 0.0;
+    s->min_rank_corr = 0.1;
+    s->judge_sample = 512;
+    s->exact_rerank = 0;
     s->mlp_seed = 0x5EED;
     ebic_mlp_defaults(&s->mlp);
     s->mlp.lr = 3e-3f;
@@ -117,6 +119,10 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
     double last_corr = -1.0;
     bool have_corr = false;
     ebic_status score_st = EBIC_OK;
+    // The judge's own stream (the run's stream is not touched).
+    SplitMix64 judge_rng(seed ^ 0xA5A5A5A5D1B54A32ull);
+    std::vector<int32_t> pool_off, pool_cols;   // the last screened pool
+    std::vector<float> pool_pred;
 
     for (;;) {
         const int32_t gen = run.generation();
@@ -124,14 +130,46 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
         int32_t pool = 0;
         bool more;
         if (screen) {
+            const int32_t need = params->population - run.elites();
             more = run.next_screened(sp->oversample, [&](const Pop &pl) {
-                std::vector<int32_t> po, pc;
-                rebase(pl, 0, po, pc);
+                rebase(pl, 0, pool_off, pool_cols);
                 std::vector<float> s((size_t)pl.size(), -INFINITY);
                 pool = pl.size();
-                ebic_status e = ebic_mlp_predict(net, po.data(), pc.data(), pl.size(), s.data());
+                ebic_status e = ebic_mlp_predict(net, pool_off.data(), pool_cols.data(),
+                                                 pl.size(), s.data());
                 if (e != EBIC_OK) score_st = e;
-                return s;
+                pool_pred = s;
+                const int64_t keep = (int64_t)sp->exact_rerank * need;
+                if (e != EBIC_OK || sp->exact_rerank <= 0 || keep >= pl.size()) return s;
+                // Two-stage screen: the network's top `keep` children are
+                // scored exactly and ranked by that score; the rest rank
+                // below them.
+                std::vector<int32_t> order((size_t)pl.size());
+                std::iota(order.begin(), order.end(), 0);
+                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                    return s[(size_t)a] > s[(size_t)b];
+                });
+                order.resize((size_t)keep);
+                std::sort(order.begin(), order.end());
+                std::vector<int32_t> ro(1, 0), rc, rcnt((size_t)keep);
+                std::vector<double> rfit((size_t)keep);
+                for (int32_t k : order) {
+                    rc.insert(rc.end(), pool_cols.begin() + pool_off[(size_t)k],
+                              pool_cols.begin() + pool_off[(size_t)k + 1]);
+                    ro.push_back((int32_t)rc.size());
+                }
+                const auto r0 = Clock::now();
+                e = ebic_evaluate(ctx, ro.data(), rc.data(), (int32_t)keep, &run.eval_params(),
+                                  nullptr, rcnt.data(), rfit.data());
+                eval_ms += ms_since(r0);
+                evaluated += keep;
+                if (e != EBIC_OK) {
+                    score_st = e;
+                    return s;
+                }
+                std::vector<float> r((size_t)pl.size(), -INFINITY);
+                for (size_t i = 0; i < order.size(); ++i) r[(size_t)order[i]] = (float)rfit[i];
+                return r;
             });
             if (score_st != EBIC_OK) return score_st;
         } else {
@@ -158,7 +196,35 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
             return st;
         eval_ms += ms_since(e0);
         evaluated += n;
-        if (gen > 0 && n > 0) {
+        if (screen && pool > 0 && sp->judge_sample > 0) {
+            // Judge on a uniform sample of the whole pool, scored exactly: the
+            // admitted children alone are a truncated sample whose rank
+            // correlation says little about the ranking of the pool.
+            const int32_t S = std::min(sp->judge_sample, pool);
+            std::vector<int32_t> pick((size_t)pool);
+            for (int32_t i = 0; i < pool; ++i) pick[(size_t)i] = i;
+            for (int32_t i = 0; i < S; ++i) {        // partial Fisher-Yates
+                const int32_t j = i + (int32_t)judge_rng.below((uint64_t)(pool - i));
+                std::swap(pick[(size_t)i], pick[(size_t)j]);
+            }
+            std::vector<int32_t> so(1, 0), sc, scnt((size_t)S);
+            std::vector<double> sfit((size_t)S), spd((size_t)S);
+            for (int32_t i = 0; i < S; ++i) {
+                const int32_t k = pick[(size_t)i];
+                sc.insert(sc.end(), pool_cols.begin() + pool_off[(size_t)k],
+                          pool_cols.begin() + pool_off[(size_t)k + 1]);
+                so.push_back((int32_t)sc.size());
+                spd[(size_t)i] = pool_pred[(size_t)k];
+            }
+            const auto j0 = Clock::now();
+            if ((st = ebic_evaluate(ctx, so.data(), sc.data(), S, &run.eval_params(), nullptr,
+                                    scnt.data(), sfit.data())) != EBIC_OK)
+                return st;
+            eval_ms += ms_since(j0);
+            evaluated += S;
+            corr = spearman(spd, sfit);
+            judged = true;
+        } else if (gen > 0 && n > 0) {
             std::vector<double> pd(pred.begin(), pred.end());
             corr = spearman(pd, fit);
             judged = true;
