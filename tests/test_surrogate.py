@@ -165,3 +165,22 @@ def test_exact_oversampled_run_matches_its_host_definition(E, small):
     _note(f"generations identical: {agree} of {len(gpu)}")
     assert agree >= 3
     assert res.biclusters
+
+
+def test_two_stage_screen_admits_exactly_scored_children(E, small):
+    # network halves the pool, exact scores rank the rest: admitted children
+    # equal the oracle and the pool judge reports a correlation
+    w, a, _ = small
+    gens, info = [], []
+    with E.Context(a) as ctx:
+        _note("two-stage screen")
+        E.evolve_surrogate(ctx, 17, 8, _cfg(E, w), on_generation=gens.append,
+                           on_surrogate=info.append, warmup_generations=2, min_rank_corr=-1.0,
+                           exact_rerank=4, train_steps=4)
+    assert sum(i["screened"] for i in info) >= 4
+    assert all(np.isfinite(i["rank_corr"]) for i in info if i["screened"])
+    for g in gens:
+        ref = oracle.evaluate(a, g.offsets, g.cols, sigma=w.sigma, max_violations=w.max_violations,
+                              negative_trends=w.negative_trends)
+        assert np.array_equal(g.counts, ref["counts"])
+        assert len(set(g.population)) == w.population
