@@ -170,6 +170,52 @@ def measured_traffic(kernel, workload):
     return int(kv["hbm_bytes_per_launch"])
 
 
+def run_sweep(args):
+    """Rows sweep of the paper's scalability experiment shape: 100 columns,
+    N = 5000 .. 25000 rows, the expression workload's planting and trend
+    parameters, P = 2048; per N the index evaluator's time and the oracle's."""
+    import dataclasses
+    import torch
+    import synth
+    import paper_1801_03039_amd as ebic
+    import oracle
+
+    dev = torch.device("cuda:0")
+    base = synth.WORKLOADS["expression"]
+    points = []
+    for n in (5000, 10000, 15000, 20000, 25000):
+        w = dataclasses.replace(base, name=f"sweep-{n}", n_rows=n, n_cols=100, seed=7)
+        a, planted = synth.make_matrix(w)
+        rng = np.random.default_rng(w.seed + 1000)
+        pop = synth.mixed_population(rng, w, planted, w.population)
+        off, cols = synth.pack_cbf(pop)
+        ctx = ebic.Context(torch.from_numpy(a).to(dev))
+        ctx.set_path("index")
+        pops = [(torch.from_numpy(off).to(dev), torch.from_numpy(cols).to(dev))]
+        wall_ms, kern_ms, _ = time_evaluations(ctx, dev, pops, w, args.steps, args.warmup)
+        P = len(pop)
+        pt = {"n_rows": n, "kernel_us": round(kern_ms * 1e3, 3),
+              "value": round(P * n / (wall_ms * 1e-3) / 1e9, 3)}
+        if not args.no_cpu:
+            kw = dict(sigma=w.sigma, max_violations=w.max_violations,
+                      negative_trends=w.negative_trends)
+            t0 = time.perf_counter()
+            ref = oracle.evaluate(a, off, cols, **kw)
+            pt["oracle_value"] = round(P * n / (time.perf_counter() - t0) / 1e9, 4)
+            got = ctx.evaluate(off, cols, **kw)
+            pt["parity"] = bool(np.array_equal(got["counts"], ref["counts"]))
+        points.append(pt)
+        log(json.dumps(pt))
+        ctx.close()
+    print(json.dumps({
+        "metric": "Gtrend-checks/s", "unit": "Gtrend-checks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rows sweep: N in 5000..25000, 100 cols, log-normal, 10 planted, "
+                               "P=2048, L 3-20, rising+falling, k=1, sigma=50"},
+        "value": points[-1]["value"], "points": points}), flush=True)
+
+
 def run_batched(args):
     """64 independent runs on matrices of uneven shapes (rows log-uniform
     500-50000, columns 20-1000), population 1024 each, one launch per step."""
@@ -447,6 +493,11 @@ def run_surrogate(args):
 
 def main():
     args = parse()
+    if args.workload == "sweep":
+        if args.gpus != 1:
+            print(json.dumps({"error": "one GPU only", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return run_sweep(args)
     if args.workload == "surrogate":
         if args.gpus != 1:
             print(json.dumps({"error": "one GPU only", "n_gpus": args.gpus}))

@@ -240,6 +240,8 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
                         int32_t words, bool copy_back = true) {
     const uint64_t tiles = fill_runs(b, q, words);
     if (tiles == 0) return EBIC_OK;
+    if (tiles > 0x7FFFFFFFull)
+        return bfail(EBIC_E_ARG, "batched populations too large for one launch; split them");
     BHIP(hipMemcpyAsync(b->d_off, b->h_off, sizeof(int32_t) * (size_t)(q.n_cand + 1),
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),

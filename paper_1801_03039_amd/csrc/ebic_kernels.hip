@@ -777,13 +777,14 @@ static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipS
 }
 
 // Tiling by matrix height.  Up to 1024 words (65536 rows) a workgroup holds
-// whole candidates, with the fewest words per lane (1, 2 or 4) that fit a
-// candidate in one workgroup: as many candidates per workgroup as fit, and
-// a workgroup just large enough (whole waves) to hold them.  Taller
-// matrices use the flattened tiling with 2 words per lane.
+// whole candidates: 1 word per lane up to 128 words, 2 up to 512 (measured
+// faster than 1 from 128 words on: half the lanes, twice the loads in
+// flight), 4 up to 1024; as many candidates per workgroup as fit, and a
+// workgroup just large enough (whole waves) to hold them.  Taller matrices
+// use the flattened tiling with 2 words per lane.
 template <int K, int U>
 static void launch_index_k(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
-    if (R.W <= kBlock)
+    if (R.W <= kBlock / 2)
         launch_aligned<K, U, 1>(R, e, ties, stream);
     else if (R.W <= 2 * kBlock)
         launch_aligned<K, U, 2>(R, e, ties, stream);
