@@ -379,14 +379,18 @@ ebic_status ebic_batch_destroy(ebic_batch *b);
 /* Launch shape of the batched kernel: `workgroups` persistent workgroups
  * draining the tile queue (0: one per resident slot; -1: one workgroup per
  * tile and no queue), `unroll` pairs per batch of loads
- * (2, 4 or 8) and `words_per_lane` 64-row words per lane (1 or 2; a tile is
- * 256 lanes, so 256 or 512 (candidate, word) pairs). */
+ * (1, 2, 4 or 8), `words_per_lane` 64-row words per lane (1, 2, 4 or 8; a tile
+ * is 256 lanes; unroll x words_per_lane at most 16) and `whole_candidates` (0: a tile is 256 consecutive
+ * (candidate, word-group) items, a candidate may span tiles; 1: a tile holds
+ * as many whole candidates as fit in 256 lanes, for runs whose candidates
+ * fit, and per-candidate counts are reduced inside the workgroup). */
 typedef struct {
     uint32_t struct_size;       /* sizeof(ebic_batch_tuning) */
     int32_t workgroups;
     int32_t unroll;
     double best_ms;             /* time of the chosen shape in the last tuning (0: untuned) */
     int32_t words_per_lane;
+    int32_t whole_candidates;
 } ebic_batch_tuning;
 ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t);
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t);

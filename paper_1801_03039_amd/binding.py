@@ -657,7 +657,7 @@ class Run:
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("workgroups", _i32), ("unroll", _i32),
-                ("best_ms", _dbl), ("words_per_lane", _i32)]
+                ("best_ms", _dbl), ("words_per_lane", _i32), ("whole_candidates", _i32)]
 
 
 BATCH_GENERATION_FN = ctypes.CFUNCTYPE(None, _vp, _i32, _i32, ctypes.POINTER(_i32),
@@ -724,11 +724,12 @@ class Batch:
         t.struct_size = ctypes.sizeof(BatchTuning)
         _check(_batch_get_tuning(self._h, ctypes.byref(t)))
         return {"workgroups": t.workgroups, "unroll": t.unroll, "best_ms": t.best_ms,
-                "words_per_lane": t.words_per_lane}
+                "words_per_lane": t.words_per_lane, "whole_candidates": t.whole_candidates}
 
-    def set_tuning(self, workgroups: int = 0, unroll: int = 4, words_per_lane: int = 1):
+    def set_tuning(self, workgroups: int = 0, unroll: int = 4, words_per_lane: int = 1,
+                   whole_candidates: int = 0):
         t = BatchTuning(ctypes.sizeof(BatchTuning), int(workgroups), int(unroll), 0.0,
-                        int(words_per_lane))
+                        int(words_per_lane), int(whole_candidates))
         _check(_batch_set_tuning(self._h, ctypes.byref(t)))
 
     def evaluate(self, pops, *, sigma: int, max_violations: int = 0,

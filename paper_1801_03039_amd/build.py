@@ -9,6 +9,7 @@ fast-math, since NaN ordering is part of the evaluator's definition.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -22,7 +23,7 @@ LIB = os.path.join(HERE, "libebic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["ebic_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
+SOURCES = ["ebic_kernels.hip", "ebic_batch_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
            "ebic_mlp_kernels.hip", "ebic_mlp.cpp", "ebic_surrogate.cpp", "ebic_scores.hip",
            "ebic_checkpoint.cpp"]
 
@@ -42,15 +43,24 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     cc = hipcc()
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD_DIR, src + ".o")
-        cmd = [cc, "-c"] + (HIP_ONLY if src.endswith(".hip") else []) + [path, "-o", obj] + COMMON
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([cc, "-c"] + (HIP_ONLY if src.endswith(".hip") else []) + [path, "-o", obj] +
+                    COMMON)
         objs.append(obj)
+    # sources compile in parallel (a few hipcc processes; the kernel files
+    # dominate the build time)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "4")), os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        procs = []
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(pool.submit(subprocess.run, cmd, check=True))
+        for f in procs:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

@@ -48,7 +48,7 @@ struct ebic_batch {
     int64_t hcap_cand = 0, hcap_cols = 0;
     // launch shape and its graph
     int32_t resident_wgs = 0;       // workgroups resident at once (occupancy x CUs)
-    int32_t workgroups = 0, unroll = 4, words = 1;
+    int32_t workgroups = 0, unroll = 4, words = 1, whole = 0;
     uint64_t static_grid = 0;   // grid of the queue-free mode (largest tile count so far)
     double tuned_ms = 0.0;
     bool tuned = false;
@@ -141,19 +141,23 @@ ebic_status reserve(ebic_batch *b, int64_t n_cand, int64_t n_cols, int64_t n_mas
 }
 
 // Fills the run table for a request (tiles of 256 lanes with `words` 64-row
-// words each); returns the total number of tiles.
-uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words) {
+// words each); returns the total number of tiles.  With `whole`, a run
+// whose candidates take at most 256 lanes each gets tiles of whole
+// candidates (as many as fit); other runs, or all without it, get tiles of
+// 256 consecutive (candidate, word-group) items.
+uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words, int32_t whole) {
     const int32_t R = (int32_t)b->ctx.size();
     int64_t cand = 0, maskw = 0;
     uint64_t tiles = 0;
     for (int32_t r = 0; r < R; ++r) {
         ebic_ctx *c = b->ctx[(size_t)r];
         const int32_t P = q.P[(size_t)r];
-        b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
-                                maskw};
-        b->h_tile_base[r] = (uint32_t)tiles;
         const uint64_t items = (uint64_t)((c->W + words - 1) / words);
-        tiles += ((uint64_t)P * items + 255) / 256;
+        const int32_t cpw = (whole && items <= 256) ? (int32_t)(256 / items) : 0;
+        b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
+                                maskw, cpw, 0};
+        b->h_tile_base[r] = (uint32_t)tiles;
+        tiles += cpw ? ((uint64_t)P + cpw - 1) / cpw : ((uint64_t)P * items + 255) / 256;
         cand += P;
         if (q.masks) maskw += (int64_t)P * 2 * c->W;
     }
@@ -237,8 +241,8 @@ ebic_status launch_graph(ebic_batch *b, const BatchLaunch &L) {
 // Runs one packed request (CBF already in h_off/h_cols, P per run set).
 // Results land in h_counts/h_fit (and d_masks when asked).
 ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
-                        int32_t words, bool copy_back = true) {
-    const uint64_t tiles = fill_runs(b, q, words);
+                        int32_t words, int32_t whole, bool copy_back = true) {
+    const uint64_t tiles = fill_runs(b, q, words, whole);
     if (tiles == 0) return EBIC_OK;
     if (tiles > 0x7FFFFFFFull)
         return bfail(EBIC_E_ARG, "batched populations too large for one launch; split them");
@@ -268,25 +272,27 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
 // the fastest (median of a few replays each).  Shapes differ only in speed:
 // every shape computes the same results.
 ebic_status tune(ebic_batch *b, const Request &q) {
-    const uint64_t tiles = fill_runs(b, q, 1);
+    const uint64_t tiles = fill_runs(b, q, 1, 0);
     if (tiles == 0) return EBIC_OK;
     const int32_t full = b->resident_wgs;
     // persistent grids, and one workgroup per tile without a queue (-1)
     std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full, -1};
-    const int32_t unrolls[] = {2, 4, 8};
-    const int32_t word_counts[] = {1, 2};
+    const int32_t unrolls[] = {1, 2, 4, 8};
+    const int32_t word_counts[] = {1, 2, 4, 8};
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     double best = 1e300;
-    int32_t best_g = full, best_u = 4, best_v = 1;
+    int32_t best_g = full, best_u = 4, best_v = 1, best_w = 0;
+    for (int32_t w = 0; w <= 1; ++w)
     for (int32_t v : word_counts)
     for (int32_t u : unrolls)
         for (int32_t g : grids) {
+            if (u * v > kMaxUnrollWords) continue;
             std::vector<float> t;
             for (int rep = 0; rep < 4; ++rep) {
                 BHIP(hipEventRecord(e0, b->stream));
-                ebic_status st = run_request(b, q, g, u, v, false);
+                ebic_status st = run_request(b, q, g, u, v, w, false);
                 if (st != EBIC_OK) return st;
                 BHIP(hipEventRecord(e1, b->stream));
                 BHIP(hipEventSynchronize(e1));
@@ -301,6 +307,7 @@ ebic_status tune(ebic_batch *b, const Request &q) {
                 best_g = g;
                 best_u = u;
                 best_v = v;
+                best_w = w;
             }
         }
     (void)hipEventDestroy(e0);
@@ -308,6 +315,7 @@ ebic_status tune(ebic_batch *b, const Request &q) {
     b->workgroups = best_g;
     b->unroll = best_u;
     b->words = best_v;
+    b->whole = best_w;
     b->tuned_ms = best;
     b->tuned = true;
     return EBIC_OK;
@@ -427,19 +435,25 @@ ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
     t->unroll = b->unroll;
     t->best_ms = b->tuned ? b->tuned_ms : 0.0;
     t->words_per_lane = b->words;
+    t->whole_candidates = b->whole;
     return EBIC_OK;
 }
 
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t) {
     if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
         return bfail(EBIC_E_ARG, "null argument or struct_size too small");
-    if (t->workgroups < -1 || (t->unroll != 2 && t->unroll != 4 && t->unroll != 8) ||
-        (t->words_per_lane != 1 && t->words_per_lane != 2))
-        return bfail(EBIC_E_ARG,
-                     "workgroups must be >= -1, unroll 2, 4 or 8 and words_per_lane 1 or 2");
+    if (t->workgroups < -1 || (t->unroll != 1 && t->unroll != 2 && t->unroll != 4 && t->unroll != 8) ||
+        (t->words_per_lane != 1 && t->words_per_lane != 2 && t->words_per_lane != 4 &&
+         t->words_per_lane != 8) ||
+        t->unroll * t->words_per_lane > kMaxUnrollWords ||
+        (t->whole_candidates != 0 && t->whole_candidates != 1))
+        return bfail(EBIC_E_ARG, "workgroups must be >= -1, unroll 1, 2, 4 or 8, words_per_lane "
+                                 "1, 2, 4 or 8 with unroll x words_per_lane <= 16, and "
+                                 "whole_candidates 0 or 1");
     b->workgroups = t->workgroups ? t->workgroups : b->resident_wgs;
     b->unroll = t->unroll;
     b->words = t->words_per_lane;
+    b->whole = t->whole_candidates;
     b->tuned = true;
     b->tuned_ms = 0.0;
     return EBIC_OK;
@@ -491,7 +505,7 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
     for (int32_t r = 0; r < R; ++r)
         if (q.P[(size_t)r]) pk.add(offsets[r], cols[r], q.P[(size_t)r]);
     if (tune_now && (st = tune(b, q)) != EBIC_OK) return st;
-    if ((st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
+    if ((st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
     int64_t cand = 0, mw = 0;
     for (int32_t r = 0; r < R; ++r) {
         const int32_t n = q.P[(size_t)r];
@@ -587,7 +601,7 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
         if (first && !b->tuned && (st = tune(b, q)) != EBIC_OK) return st;
         first = false;
         const auto e0 = std::chrono::steady_clock::now();
-        if ((st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
+        if ((st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
         eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
         evaluated += q.n_cand;
         std::vector<int64_t> base((size_t)R + 1, 0);
@@ -622,7 +636,7 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
     for (int32_t r = 0; r < R; ++r)
         if (q.P[(size_t)r]) pk.add(tops[(size_t)r].off.data(), tops[(size_t)r].cols.data(), q.P[(size_t)r]);
     const auto e0 = std::chrono::steady_clock::now();
-    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll, b->words)) != EBIC_OK) return st;
+    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
     std::vector<uint64_t> all_masks((size_t)std::max<int64_t>(n_mask, 1));
     if (n_mask)
         BHIP(hipMemcpy(all_masks.data(), b->d_masks, sizeof(uint64_t) * (size_t)n_mask,

@@ -58,7 +58,12 @@ struct IndexRun {
     int32_t P;               // candidates of the run in this launch
     int64_t cand_base;       // index of the run's first candidate in the launch
     int64_t mask_base;       // first mask word of the run (when masks are written)
+    int32_t cpw;             // batched tiles: whole candidates per tile (0: flattened tiles)
+    int32_t reserved;
 };
+
+// Batched launch shapes: unroll x words per lane is at most this.
+constexpr int kMaxUnrollWords = 16;
 
 // A persistent multi-run launch.  runs/tile_base/work are device arrays;
 // tile_base[r] is the first tile of run r (tile_base[n_runs] = total);

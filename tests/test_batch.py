@@ -123,22 +123,54 @@ def test_every_launch_shape_agrees(E, mats):
         ref = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True, want_masks=True,
                          tune=True)
         t = b.tuning()
-        assert t["unroll"] in (2, 4, 8) and (t["workgroups"] >= 1 or t["workgroups"] == -1)
+        assert t["unroll"] in (1, 2, 4, 8) and (t["workgroups"] >= 1 or t["workgroups"] == -1)
         assert t["best_ms"] > 0
-        assert t["words_per_lane"] in (1, 2)
+        assert t["words_per_lane"] in (1, 2, 4, 8) and t["whole_candidates"] in (0, 1)
+        assert t["unroll"] * t["words_per_lane"] <= 16
         _check_runs(mats, pops, ref, 5, 2, True)
         for wg in (1, 0, 7, 5000, -1):
-            for u in (2, 4, 8):
-                for v in (1, 2):
-                    _note(f"shape wg={wg} unroll={u} words={v}")
-                    b.set_tuning(wg, u, v)
-                    got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
+            for u in (1, 2, 4, 8):
+                for v in (1, 2, 4, 8):
+                    if u * v > 16:
+                        with pytest.raises(E.EbicError):
+                            b.set_tuning(wg, u, v, 0)
+                        continue
+                    for whole in (0, 1):
+                        _note(f"shape wg={wg} unroll={u} words={v} whole={whole}")
+                        b.set_tuning(wg, u, v, whole)
+                        got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
+                                         want_masks=True)
+                        for g, r in zip(got, ref):
+                            assert np.array_equal(g["counts"], r["counts"])
+                            assert np.array_equal(g["fitness"].view(np.int64),
+                                                  r["fitness"].view(np.int64))
+                            assert np.array_equal(g["masks"], r["masks"])
+
+
+def test_whole_candidate_tiles_on_tall_and_short_runs(E):
+    # Runs on both sides of the whole-candidate limit (256 lanes: 16384 rows
+    # at one word per lane, 32768 at two, 65536 at four) in one launch, tied
+    # and untied matrices, against the oracle; each tiling mode in turn.
+    rng = np.random.default_rng(6)
+    shapes = [(16384, 9), (16385, 7), (32768, 6), (32769, 5), (65536, 4), (65537, 5),
+              (70, 40), (1, 3)]
+    mats_ = [synth.adversarial_matrix(rng, *s) if i % 2 else
+             rng.standard_normal(s).astype(np.float32) for i, s in enumerate(shapes)]
+    pops = []
+    for a in mats_:
+        m = a.shape[1]
+        pop = synth.random_population(rng, m, int(rng.integers(20, 120)), 1, min(m, 8))
+        off, cols = synth.pack_cbf(pop)
+        pops.append((off, cols))
+    with E.Batch(mats_) as b:
+        for v in (1, 2, 4, 8):
+            for whole in (0, 1):
+                for wg in (0, -1):
+                    _note(f"tall/short runs words={v} whole={whole} wg={wg}")
+                    b.set_tuning(wg, min(4, 16 // v), v, whole)
+                    got = b.evaluate(pops, sigma=4, max_violations=1, negative_trends=True,
                                      want_masks=True)
-                    for g, r in zip(got, ref):
-                        assert np.array_equal(g["counts"], r["counts"])
-                        assert np.array_equal(g["fitness"].view(np.int64),
-                                              r["fitness"].view(np.int64))
-                        assert np.array_equal(g["masks"], r["masks"])
+                    _check_runs(mats_, pops, got, 4, 1, True)
 
 
 def test_batch_errors(E, mats):
