@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--evolve-gens", type=int, default=-1, help="generations (-1: workload's)")
     ap.add_argument("--surrogate-seeds", type=int, default=3,
                     help="seeds of the plain-vs-surrogate comparison (--workload surrogate)")
+    ap.add_argument("--batch-shape", default="",
+                    help="batched workload: fixed launch shape 'workgroups,unroll,words,whole' "
+                         "instead of the autotuner")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one device copy of this many MiB (a kernel of "
                          "known traffic, to calibrate rocprof FETCH_SIZE/WRITE_SIZE)")
@@ -163,6 +166,11 @@ def kernel_source_sha(kernel="eval_index_kernel"):
     return h.hexdigest()
 
 
+def batch_shape(t):
+    """'workgroups,unroll,words,whole' of a batched launch shape."""
+    return f"{t['workgroups']},{t['unroll']},{t['words_per_lane']},{t['whole_candidates']}"
+
+
 def calibration_copy(args, dev):
     """A plain device copy of --copy-mb MiB (the reference point that scales
     the FETCH_SIZE / WRITE_SIZE counters in the traffic summaries)."""
@@ -175,10 +183,11 @@ def calibration_copy(args, dev):
         del src, dst
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, shape=None):
     """HBM bytes per launch from the committed rocprof counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
-    when it was not taken on the current kernel source."""
+    when it was not taken on the current kernel source (or, for a batched
+    launch, on the launch shape in use)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -188,6 +197,8 @@ def measured_traffic(kernel, workload):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_sha(kernel):
+        return None
+    if shape is not None and kv.get("launch_shape") != shape:
         return None
     return int(kv["hbm_bytes_per_launch"])
 
@@ -256,8 +267,11 @@ def run_batched(args):
     t0 = time.perf_counter()
     b = ebic.Batch([a for a, _ in data])
     create_ms = (time.perf_counter() - t0) * 1e3
-    log("batched: tuning")
-    b.evaluate(pops, sigma=25, tune=True)
+    if args.batch_shape:
+        b.set_tuning(*[int(x) for x in args.batch_shape.split(",")])
+    else:
+        log("batched: tuning")
+        b.evaluate(pops, sigma=25, tune=True)
     tuning = b.tuning()
     for _ in range(args.warmup):
         b.evaluate(pops, sigma=25)
@@ -267,7 +281,9 @@ def run_batched(args):
         b.evaluate(pops, sigma=25)
         dev.append(b.last_ms())
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    dev_ms = float(np.median(dev))
+    call_dev_ms = float(np.median(dev))
+    # the kernel's duration: the last launch replayed back to back
+    dev_ms = b.time_replays(args.steps)
     calibration_copy(args, torch.device("cuda", 0))
     out = {
         "metric": "Gtrend-checks/s, candidates/s vs plain; surrogate speedup at equal fitness",
@@ -280,6 +296,7 @@ def run_batched(args):
                    "trend_checks_per_step": checks},
         "step_includes": "host CBF upload and result download of all runs (PCIe) + one launch",
         "device_ms_per_launch": round(dev_ms, 4),
+        "device_ms_per_call": round(call_dev_ms, 4),
         "device_value": round(checks / (dev_ms * 1e-3) / 1e9, 3),
         "tuning": tuning, "create_ms": round(create_ms, 1),
     }
@@ -320,10 +337,12 @@ def run_batched(args):
         achieved = b_alg / (dev_ms * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic("eval_index_batch_kernel", "batched"),
+                           "traffic": measured_traffic("eval_index_batch_kernel", "batched",
+                                                       batch_shape(tuning)),
                            "kernel": "eval_index_batch_kernel",
                            "bytes_per_launch": b_alg,
-                           "duration": "device time of the launch graph (run-table copy + kernel)"}
+                           "duration": "kernel time: events on the batch stream around back-to-back "
+                                       "replays of the timed launch"}
     b.close()
     print(json.dumps(out), flush=True)
 

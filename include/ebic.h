@@ -383,7 +383,10 @@ ebic_status ebic_batch_destroy(ebic_batch *b);
  * is 256 lanes; unroll x words_per_lane at most 16) and `whole_candidates` (0: a tile is 256 consecutive
  * (candidate, word-group) items, a candidate may span tiles; 1: a tile holds
  * as many whole candidates as fit in 256 lanes, for runs whose candidates
- * fit, and per-candidate counts are reduced inside the workgroup). */
+ * fit, and per-candidate counts are reduced inside the workgroup).
+ * `use_graph` = 1 replays the kernel as a captured one-node HIP graph
+ * (re-captured when a buffer or the shape changes); 0 (default) launches it
+ * directly.  The autotuner sets the first four fields and keeps use_graph. */
 typedef struct {
     uint32_t struct_size;       /* sizeof(ebic_batch_tuning) */
     int32_t workgroups;
@@ -391,6 +394,7 @@ typedef struct {
     double best_ms;             /* time of the chosen shape in the last tuning (0: untuned) */
     int32_t words_per_lane;
     int32_t whole_candidates;
+    int32_t use_graph;
 } ebic_batch_tuning;
 ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t);
 ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t);
@@ -416,9 +420,17 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
  * here, called with the run index, one call at a time).  host_threads <= 0
  * picks the hardware concurrency.  The launch shape is tuned on the first
  * generation unless set before. */
-/* Device time (ms) of the last batched launch: the run-table copy and the
- * persistent kernel, from events on the batch's stream around the graph. */
+/* Device time (ms) of the last batched launch: the kernel, from events on
+ * the batch's stream around its launch (the run table is copied before). */
 double ebic_batch_last_ms(const ebic_batch *b);
+/* Replays the last batched launch `reps` times back to back on the batch's
+ * stream (same inputs, same results written again) and stores the mean
+ * device time per launch in ms, from events around the replays: the
+ * kernel's own duration without per-call copies and synchronisation, for
+ * profiling and launch-shape comparisons (the autotuner uses it).  Errors:
+ * E_ARG (null, reps < 1, or no launch since the batch was created or since
+ * a request with no candidates), E_DEVICE. */
+ebic_status ebic_batch_time_replays(ebic_batch *b, int32_t reps, double *ms_per_launch);
 
 typedef void (*ebic_batch_generation_fn)(void *user, int32_t run, int32_t gen,
                                          const int32_t *offsets, const int32_t *cols, int32_t P,

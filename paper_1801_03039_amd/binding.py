@@ -657,7 +657,8 @@ class Run:
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("workgroups", _i32), ("unroll", _i32),
-                ("best_ms", _dbl), ("words_per_lane", _i32), ("whole_candidates", _i32)]
+                ("best_ms", _dbl), ("words_per_lane", _i32), ("whole_candidates", _i32),
+                ("use_graph", _i32)]
 
 
 BATCH_GENERATION_FN = ctypes.CFUNCTYPE(None, _vp, _i32, _i32, ctypes.POINTER(_i32),
@@ -672,7 +673,8 @@ _batch_evaluate = _sig("ebic_batch_evaluate", _i32,
 _batch_evolve = _sig("ebic_batch_evolve", _i32,
                      [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _i32, _vp])
 _batch_last_ms = _sig("ebic_batch_last_ms", _dbl, [_vp])
-EXPORTED += ["ebic_batch_last_ms", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
+_batch_time_replays = _sig("ebic_batch_time_replays", _i32, [_vp, _i32, _P(_dbl)])
+EXPORTED += ["ebic_batch_last_ms", "ebic_batch_time_replays", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
              "ebic_batch_set_tuning", "ebic_batch_evaluate", "ebic_batch_evolve"]
 
 
@@ -716,20 +718,27 @@ class Batch:
         self.close()
 
     def last_ms(self) -> float:
-        """Device time of the last batched launch (run-table copy + kernel)."""
+        """Device time (ms) of the last batched launch (the kernel)."""
         return float(_batch_last_ms(self._h))
+
+    def time_replays(self, reps: int) -> float:
+        """Mean device ms of ``reps`` back-to-back replays of the last launch."""
+        ms = _dbl()
+        _check(_batch_time_replays(self._h, int(reps), ctypes.byref(ms)))
+        return float(ms.value)
 
     def tuning(self) -> dict:
         t = BatchTuning()
         t.struct_size = ctypes.sizeof(BatchTuning)
         _check(_batch_get_tuning(self._h, ctypes.byref(t)))
         return {"workgroups": t.workgroups, "unroll": t.unroll, "best_ms": t.best_ms,
-                "words_per_lane": t.words_per_lane, "whole_candidates": t.whole_candidates}
+                "words_per_lane": t.words_per_lane, "whole_candidates": t.whole_candidates,
+                "use_graph": t.use_graph}
 
     def set_tuning(self, workgroups: int = 0, unroll: int = 4, words_per_lane: int = 1,
-                   whole_candidates: int = 0):
+                   whole_candidates: int = 0, use_graph: int = 0):
         t = BatchTuning(ctypes.sizeof(BatchTuning), int(workgroups), int(unroll), 0.0,
-                        int(words_per_lane), int(whole_candidates))
+                        int(words_per_lane), int(whole_candidates), int(use_graph))
         _check(_batch_set_tuning(self._h, ctypes.byref(t)))
 
     def evaluate(self, pops, *, sigma: int, max_violations: int = 0,

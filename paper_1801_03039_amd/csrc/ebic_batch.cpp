@@ -4,10 +4,12 @@
 // Per generation every active run builds its population on a host thread
 // (Steps 1-3); the new members of all runs are packed into one CBF with
 // global offsets, a run table describes where each run's candidates,
-// matrix index and outputs are, and one persistent kernel drains the queue
-// of (run, 64-row word) tiles (Step 4).  The run-table copy and the kernel
-// are a captured HIP graph, replayed each generation; the CBF and results
-// move with plain stream-ordered copies around it.  Step 5 then runs per
+// matrix index and outputs are, and one kernel covers the (run, candidate,
+// 64-row word) tiles (Step 4).  The run table lives in device memory and is
+// rewritten by one copy per generation; the kernel is launched directly or
+// as a captured one-node HIP graph replayed each generation (use_graph),
+// with the CBF and results moving by stream-ordered copies around it.
+// Step 5 then runs per
 // run on host threads.  Every run is exactly ebic_evolve on its own
 // context: same seed, same draws, same scores.
 #include <hip/hip_runtime.h>
@@ -32,8 +34,8 @@ struct ebic_batch {
     hipStream_t stream = nullptr;
     std::vector<ebic_ctx *> ctx;
     // device buffers
-    IndexRun *d_runs = nullptr;
-    uint32_t *d_tile_base = nullptr;
+    IndexRun *d_runs = nullptr;          // run table, then the tile bases (one allocation)
+    uint32_t *d_tile_base = nullptr;     // inside the d_runs allocation
     unsigned int *d_work = nullptr;
     int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr;
     double *d_fit = nullptr;
@@ -41,14 +43,14 @@ struct ebic_batch {
     uint64_t *d_masks = nullptr;
     int64_t cap_cand = 0, cap_cols = 0, cap_masks = 0;
     // pinned host staging
-    IndexRun *h_runs = nullptr;
+    IndexRun *h_runs = nullptr;          // same layout as d_runs
     uint32_t *h_tile_base = nullptr;
     int32_t *h_off = nullptr, *h_cols = nullptr, *h_counts = nullptr;
     double *h_fit = nullptr;
     int64_t hcap_cand = 0, hcap_cols = 0;
     // launch shape and its graph
     int32_t resident_wgs = 0;       // workgroups resident at once (occupancy x CUs)
-    int32_t workgroups = 0, unroll = 4, words = 1, whole = 0;
+    int32_t workgroups = 0, unroll = 4, words = 1, whole = 0, use_graph = 0;
     uint64_t static_grid = 0;   // grid of the queue-free mode (largest tile count so far)
     double tuned_ms = 0.0;
     bool tuned = false;
@@ -56,6 +58,8 @@ struct ebic_batch {
     BatchLaunch graph_key{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the last graph launch
     double last_ms = 0.0;
+    BatchLaunch last_launch{};   // the last launch (replayed by ebic_batch_time_replays)
+    bool has_last = false;
 };
 
 namespace {
@@ -140,6 +144,11 @@ ebic_status reserve(ebic_batch *b, int64_t n_cand, int64_t n_cols, int64_t n_mas
     return hgrow(b, b->h_cols, std::max<int64_t>(n_cols, 1), b->hcap_cols);
 }
 
+// Bytes of the run table of n runs followed by its n + 1 tile bases.
+size_t run_table_bytes(int32_t n_runs) {
+    return sizeof(IndexRun) * (size_t)n_runs + sizeof(uint32_t) * ((size_t)n_runs + 1);
+}
+
 // Fills the run table for a request (tiles of 256 lanes with `words` 64-row
 // words each); returns the total number of tiles.  With `whole`, a run
 // whose candidates take at most 256 lanes each gets tiles of whole
@@ -165,9 +174,11 @@ uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words, int32_t whole
     return tiles;
 }
 
-// workgroups < 0: one workgroup per tile, no queue; the grid is the largest
-// tile count seen so far (the kernel reads the current count), so that the
-// captured graph stays valid from one generation to the next.
+// workgroups < 0: one workgroup per tile, no queue.  A direct launch has
+// exactly one workgroup per tile; a graph launch uses the largest tile count
+// seen since the shape was set (the kernel reads the current count, and
+// surplus workgroups return at once), so that the captured graph stays valid
+// from one generation to the next.
 BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
                         int32_t words, uint64_t tiles) {
     BatchLaunch L{};
@@ -188,9 +199,11 @@ BatchLaunch make_launch(ebic_batch *b, const Request &q, int32_t workgroups, int
     L.acc = b->d_acc;
     L.counts = b->d_counts;
     L.fitness = b->d_fit;
-    if (workgroups < 0) {
+    if (workgroups < 0 && b->use_graph) {
         b->static_grid = std::max<uint64_t>(b->static_grid, tiles);
         L.grid = (uint32_t)b->static_grid;
+    } else if (workgroups < 0) {
+        L.grid = (uint32_t)tiles;
     } else {
         L.grid = (uint32_t)workgroups;
     }
@@ -208,19 +221,13 @@ bool same_graph(const BatchLaunch &a, const BatchLaunch &x) {
            a.unroll == x.unroll && a.words == x.words;
 }
 
-// Graph = [copy of the run table and tile bases (fixed size), kernel].
+// Graph = [kernel]; the run table is copied before it on the same stream.
 ebic_status launch_graph(ebic_batch *b, const BatchLaunch &L) {
-    const size_t R = b->ctx.size();
     if (!b->exec || !same_graph(b->graph_key, L)) {
         drop_graph(b);
         hipGraph_t g = nullptr;
         BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipMemcpyAsync(b->d_runs, b->h_runs, sizeof(IndexRun) * R,
-                                      hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->d_tile_base, b->h_tile_base, sizeof(uint32_t) * (R + 1),
-                               hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess) e = launch_eval_index_batch(L, b->stream);
+        hipError_t e = launch_eval_index_batch(L, b->stream);
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -238,10 +245,35 @@ ebic_status launch_graph(ebic_batch *b, const BatchLaunch &L) {
     return EBIC_OK;
 }
 
+ebic_status launch(ebic_batch *b, const BatchLaunch &L) {
+    if (b->use_graph) return launch_graph(b, L);
+    BHIP(launch_eval_index_batch(L, b->stream));
+    return EBIC_OK;
+}
+
+// Mean device time of `reps` back-to-back launches of the last request
+// (same inputs and outputs; the kernel leaves its queue and accumulators
+// as it found them).
+ebic_status time_replays(ebic_batch *b, int32_t reps, double *ms_per_launch) {
+    if (!b->has_last) return bfail(EBIC_E_ARG, "no batched launch to replay");
+    BHIP(hipEventRecord(b->ev0, b->stream));
+    for (int32_t i = 0; i < reps; ++i) {
+        ebic_status st = launch(b, b->last_launch);
+        if (st != EBIC_OK) return st;
+    }
+    BHIP(hipEventRecord(b->ev1, b->stream));
+    BHIP(hipEventSynchronize(b->ev1));
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    *ms_per_launch = (double)ms / reps;
+    return EBIC_OK;
+}
+
 // Runs one packed request (CBF already in h_off/h_cols, P per run set).
 // Results land in h_counts/h_fit (and d_masks when asked).
 ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
                         int32_t words, int32_t whole, bool copy_back = true) {
+    b->has_last = false;
     const uint64_t tiles = fill_runs(b, q, words, whole);
     if (tiles == 0) return EBIC_OK;
     if (tiles > 0x7FFFFFFFull)
@@ -250,10 +282,15 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->d_cols, b->h_cols, sizeof(int32_t) * (size_t)std::max<int64_t>(q.n_cols, 1),
                         hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->d_runs, b->h_runs, run_table_bytes((int32_t)b->ctx.size()),
+                        hipMemcpyHostToDevice, b->stream));
     BHIP(hipEventRecord(b->ev0, b->stream));
-    ebic_status st = launch_graph(
-        b, make_launch(b, q, workgroups < 0 ? -1 : std::max(1, workgroups), unroll, words, tiles));
+    const BatchLaunch L =
+        make_launch(b, q, workgroups < 0 ? -1 : std::max(1, workgroups), unroll, words, tiles);
+    ebic_status st = launch(b, L);
     if (st != EBIC_OK) return st;
+    b->last_launch = L;
+    b->has_last = true;
     BHIP(hipEventRecord(b->ev1, b->stream));
     if (copy_back) {
         BHIP(hipMemcpyAsync(b->h_counts, b->d_counts, sizeof(int32_t) * (size_t)q.n_cand,
@@ -269,8 +306,11 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
 }
 
 // Autotuner: times candidate launch shapes on this very request and keeps
-// the fastest (median of a few replays each).  Shapes differ only in speed:
-// every shape computes the same results.
+// the fastest (mean of back-to-back replays of each shape after one
+// launch that uploads its run table).  Shapes differ only in speed: every
+// shape computes the same results.
+constexpr int32_t kTuneReplays = 5;
+
 ebic_status tune(ebic_batch *b, const Request &q) {
     const uint64_t tiles = fill_runs(b, q, 1, 0);
     if (tiles == 0) return EBIC_OK;
@@ -279,9 +319,6 @@ ebic_status tune(ebic_batch *b, const Request &q) {
     std::vector<int32_t> grids = {std::max(1, full / 2), full, 2 * full, -1};
     const int32_t unrolls[] = {1, 2, 4, 8};
     const int32_t word_counts[] = {1, 2, 4, 8};
-    hipEvent_t e0, e1;
-    BHIP(hipEventCreate(&e0));
-    BHIP(hipEventCreate(&e1));
     double best = 1e300;
     int32_t best_g = full, best_u = 4, best_v = 1, best_w = 0;
     for (int32_t w = 0; w <= 1; ++w)
@@ -289,19 +326,10 @@ ebic_status tune(ebic_batch *b, const Request &q) {
     for (int32_t u : unrolls)
         for (int32_t g : grids) {
             if (u * v > kMaxUnrollWords) continue;
-            std::vector<float> t;
-            for (int rep = 0; rep < 4; ++rep) {
-                BHIP(hipEventRecord(e0, b->stream));
-                ebic_status st = run_request(b, q, g, u, v, w, false);
-                if (st != EBIC_OK) return st;
-                BHIP(hipEventRecord(e1, b->stream));
-                BHIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                BHIP(hipEventElapsedTime(&ms, e0, e1));
-                t.push_back(ms);
-            }
-            std::sort(t.begin(), t.end());
-            const double med = 0.5 * (t[1] + t[2]);
+            ebic_status st = run_request(b, q, g, u, v, w, false);
+            double med = 0.0;
+            if (st == EBIC_OK) st = time_replays(b, kTuneReplays, &med);
+            if (st != EBIC_OK) return st;
             if (med < best) {
                 best = med;
                 best_g = g;
@@ -310,12 +338,11 @@ ebic_status tune(ebic_batch *b, const Request &q) {
                 best_w = w;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     b->workgroups = best_g;
     b->unroll = best_u;
     b->words = best_v;
     b->whole = best_w;
+    b->static_grid = 0;
     b->tuned_ms = best;
     b->tuned = true;
     return EBIC_OK;
@@ -386,16 +413,16 @@ ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, cons
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e != hipSuccess) return cleanup(bhip(e, "batch stream"));
-    if ((e = hipMalloc((void **)&b->d_runs, sizeof(IndexRun) * (size_t)n_runs)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_tile_base, sizeof(uint32_t) * ((size_t)n_runs + 1))) !=
-            hipSuccess ||
+    // The run table and the tile bases share one allocation on each side,
+    // so that one copy node per launch carries both.
+    const size_t table = run_table_bytes(n_runs);
+    if ((e = hipMalloc((void **)&b->d_runs, table)) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_work, sizeof(unsigned int) * 2)) != hipSuccess ||
         (e = hipMemset(b->d_work, 0, sizeof(unsigned int) * 2)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_runs, sizeof(IndexRun) * (size_t)n_runs,
-                           hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_tile_base, sizeof(uint32_t) * ((size_t)n_runs + 1),
-                           hipHostMallocDefault)) != hipSuccess)
+        (e = hipHostMalloc((void **)&b->h_runs, table, hipHostMallocDefault)) != hipSuccess)
         return cleanup(bhip(e, "batch buffers"));
+    b->d_tile_base = reinterpret_cast<uint32_t *>(b->d_runs + n_runs);
+    b->h_tile_base = reinterpret_cast<uint32_t *>(b->h_runs + n_runs);
     int cus = 0;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) !=
         hipSuccess)
@@ -411,11 +438,11 @@ ebic_status ebic_batch_destroy(ebic_batch *b) {
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    void *dev[] = {b->d_runs, b->d_tile_base, b->d_work, b->d_off, b->d_cols, b->d_counts,
+    void *dev[] = {b->d_runs, b->d_work, b->d_off, b->d_cols, b->d_counts,
                    b->d_fit, b->d_acc, b->d_masks};
     for (void *p : dev)
         if (p) (void)hipFree(p);
-    void *host[] = {b->h_runs, b->h_tile_base, b->h_off, b->h_cols, b->h_counts, b->h_fit};
+    void *host[] = {b->h_runs, b->h_off, b->h_cols, b->h_counts, b->h_fit};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
@@ -428,6 +455,12 @@ ebic_status ebic_batch_destroy(ebic_batch *b) {
 
 double ebic_batch_last_ms(const ebic_batch *b) { return b ? b->last_ms : 0.0; }
 
+ebic_status ebic_batch_time_replays(ebic_batch *b, int32_t reps, double *ms_per_launch) {
+    if (!b || !ms_per_launch || reps < 1) return bfail(EBIC_E_ARG, "null argument or reps < 1");
+    BHIP(hipSetDevice(b->device));
+    return time_replays(b, reps, ms_per_launch);
+}
+
 ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
     if (!b || !t || t->struct_size < sizeof(ebic_batch_tuning))
         return bfail(EBIC_E_ARG, "null argument or struct_size too small");
@@ -436,6 +469,7 @@ ebic_status ebic_batch_get_tuning(const ebic_batch *b, ebic_batch_tuning *t) {
     t->best_ms = b->tuned ? b->tuned_ms : 0.0;
     t->words_per_lane = b->words;
     t->whole_candidates = b->whole;
+    t->use_graph = b->use_graph;
     return EBIC_OK;
 }
 
@@ -446,14 +480,17 @@ ebic_status ebic_batch_set_tuning(ebic_batch *b, const ebic_batch_tuning *t) {
         (t->words_per_lane != 1 && t->words_per_lane != 2 && t->words_per_lane != 4 &&
          t->words_per_lane != 8) ||
         t->unroll * t->words_per_lane > kMaxUnrollWords ||
-        (t->whole_candidates != 0 && t->whole_candidates != 1))
+        (t->whole_candidates != 0 && t->whole_candidates != 1) ||
+        (t->use_graph != 0 && t->use_graph != 1))
         return bfail(EBIC_E_ARG, "workgroups must be >= -1, unroll 1, 2, 4 or 8, words_per_lane "
-                                 "1, 2, 4 or 8 with unroll x words_per_lane <= 16, and "
-                                 "whole_candidates 0 or 1");
+                                 "1, 2, 4 or 8 with unroll x words_per_lane <= 16, "
+                                 "whole_candidates and use_graph 0 or 1");
     b->workgroups = t->workgroups ? t->workgroups : b->resident_wgs;
     b->unroll = t->unroll;
     b->words = t->words_per_lane;
     b->whole = t->whole_candidates;
+    b->use_graph = t->use_graph;
+    b->static_grid = 0;
     b->tuned = true;
     b->tuned_ms = 0.0;
     return EBIC_OK;

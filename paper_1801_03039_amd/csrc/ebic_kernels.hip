@@ -314,19 +314,23 @@ static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipS
 }
 
 // Tiling by matrix height.  Up to 1024 words (65536 rows) a workgroup holds
-// whole candidates: 1 word per lane up to 128 words, 2 up to 512 (measured
+// whole candidates: 1 word per lane up to 128 words, 2 up to 320 (measured
 // faster than 1 from 128 words on: half the lanes, twice the loads in
-// flight), 4 up to 1024; as many candidates per workgroup as fit, and a
-// workgroup just large enough (whole waves) to hold them.  Taller matrices
-// use the flattened tiling with 2 words per lane.
+// flight), 4 with 2 pairs per batch of loads up to 1024 (measured 7-13%
+// faster than 2 words from 391 to 1016 words, equal at 344); as many
+// candidates per workgroup as fit, and a workgroup just large enough (whole
+// waves) to hold them.  Taller matrices use the flattened tiling with 2
+// words per lane.
+constexpr int64_t kTwoWordsMax = 320;
+
 template <int K, int U>
 static void launch_index_k(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
     if (R.W <= kBlock / 2)
         launch_aligned<K, U, 1>(R, e, ties, stream);
-    else if (R.W <= 2 * kBlock)
+    else if (R.W <= kTwoWordsMax)
         launch_aligned<K, U, 2>(R, e, ties, stream);
     else if (R.W <= 4 * kBlock)
-        launch_aligned<K, U, 4>(R, e, ties, stream);
+        launch_aligned<K, 2, 4>(R, e, ties, stream);
     else {
         constexpr int V = kWordsPerLane;
         const int64_t total = (int64_t)R.P * ((R.W + V - 1) / V);

@@ -97,16 +97,19 @@ def test_full_batched_configuration(E):
         assert np.array_equal(g2["counts"], ref["counts"])
 
 
-def test_graph_replays_interleaved_with_eager_work(E, mats):
-    # The captured graph is replayed with a new run table each time, with
-    # eager single-context work and host synchronisation in between; every
-    # replay must equal the oracle.
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_graph_replays_interleaved_with_eager_work(E, mats, use_graph):
+    # The captured graph (or the direct launch) is replayed with a new run
+    # table each time, with eager single-context work and host
+    # synchronisation in between; every replay must equal the oracle.
     import torch
     rng = np.random.default_rng(2)
     with E.Batch(mats) as b, E.Context(mats[3]) as ctx:
+        b.set_tuning(0, 4, 1, 0, use_graph)
+        assert b.tuning()["use_graph"] == use_graph
         for rep in range(5):
             pops = _pops(rng, mats)
-            _note(f"replay {rep}")
+            _note(f"replay {rep} use_graph={use_graph}")
             got = b.evaluate(pops, sigma=4, max_violations=1, negative_trends=True)
             _check_runs(mats, pops, got, 4, 1, True, masks=False)
             eager = ctx.evaluate(*pops[3], sigma=4, max_violations=1, negative_trends=True)
@@ -136,8 +139,9 @@ def test_every_launch_shape_agrees(E, mats):
                             b.set_tuning(wg, u, v, 0)
                         continue
                     for whole in (0, 1):
-                        _note(f"shape wg={wg} unroll={u} words={v} whole={whole}")
-                        b.set_tuning(wg, u, v, whole)
+                        g = (u + v + whole) % 2
+                        _note(f"shape wg={wg} unroll={u} words={v} whole={whole} graph={g}")
+                        b.set_tuning(wg, u, v, whole, g)
                         got = b.evaluate(pops, sigma=5, max_violations=2, negative_trends=True,
                                          want_masks=True)
                         for g, r in zip(got, ref):
@@ -175,12 +179,35 @@ def test_whole_candidate_tiles_on_tall_and_short_runs(E):
 
 def test_batch_errors(E, mats):
     with E.Batch(mats[:2]) as b:
+        with pytest.raises(E.EbicError):
+            b.time_replays(3)          # nothing launched yet
         bad = [(np.array([0, 2]), np.array([0, 99])), None]
         with pytest.raises(E.EbicError):
             b.evaluate(bad, sigma=1)
         with pytest.raises(E.EbicError):
             b.evaluate([None, None], sigma=1, max_violations=4)
         assert b.evaluate([None, None], sigma=1) == [None, None]
+        with pytest.raises(E.EbicError):
+            b.time_replays(3)          # the last request launched nothing
+
+
+def test_replays_keep_state(E, mats):
+    # Back-to-back replays of a launch (queue and accumulators left as
+    # found) do not disturb later launches, in every tiling mode.
+    rng = np.random.default_rng(7)
+    with E.Batch(mats) as b:
+        for wg, u, v, whole in ((0, 4, 1, 0), (-1, 2, 2, 0), (-1, 1, 8, 1), (7, 2, 4, 1)):
+            b.set_tuning(wg, u, v, whole)
+            pops = _pops(rng, mats)
+            b.evaluate(pops, sigma=3, max_violations=1, negative_trends=True)
+            with pytest.raises(E.EbicError):
+                b.time_replays(0)
+            _note(f"replays wg={wg} u={u} v={v} whole={whole}")
+            assert b.time_replays(5) > 0
+            pops2 = _pops(rng, mats)
+            got = b.evaluate(pops2, sigma=3, max_violations=1, negative_trends=True,
+                             want_masks=True)
+            _check_runs(mats, pops2, got, 3, 1, True)
 
 
 def test_batch_evolve_matches_oracle_runs(E):
