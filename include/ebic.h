@@ -361,10 +361,11 @@ void ebic_run_destroy(ebic_run *r);
  * Batched EBIC: many independent runs, each on its own matrix (any shapes),
  * sharing one GPU launch per generation.  Each run behaves exactly as
  * ebic_evolve on its own context with its own seed; the runs' populations
- * are evaluated together by one persistent kernel that drains a queue of
- * (run, candidate, 64-row word) tiles, launched through a captured HIP graph
- * whose run table is refreshed in device memory each generation.  The host
- * steps of the runs proceed on host threads.  Evaluation uses each run's
+ * are evaluated together by one kernel over tiles of (run, candidate,
+ * 64-row words), either one workgroup per tile or persistent workgroups
+ * draining a tile queue, launched directly or as a captured HIP graph; the
+ * run table lives in device memory and is refreshed each generation.  The
+ * host steps of the runs proceed on host threads.  Evaluation uses each run's
  * pairwise order index (built at creation), so max_violations <= 3.
  */
 typedef struct ebic_batch ebic_batch;

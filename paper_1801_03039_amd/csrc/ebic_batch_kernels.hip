@@ -9,13 +9,15 @@ namespace {
 
 // --------------------------------------------------- batched (many runs) --
 //
-// One persistent launch evaluates one population per run for many runs with
-// matrices of different shapes.  The work is a queue of tiles (kBlock
-// consecutive (candidate, word) items of one run), run after run; each
-// workgroup takes the next tile with an atomic until the queue is empty.
-// The last workgroup to leave resets the queue, so the launch can be
-// replayed (a captured graph) without any clearing step.  work[0] is the
-// next tile, work[1] the number of workgroups that have left.
+// One launch evaluates one population per run for many runs with matrices
+// of different shapes.  The work is a list of tiles, run after run: a tile
+// is kBlock lanes of one run holding V words each, either whole candidates
+// (the run's cpw > 0) or consecutive (candidate, word-group) items.  With
+// `work`, persistent workgroups take the next tile with an atomic until the
+// list is exhausted, and the last workgroup to leave resets the queue, so
+// the launch can be replayed (a captured graph) without any clearing step;
+// work[0] is the next tile, work[1] the number of workgroups that have
+// left.  Without it, workgroup b takes tile b (surplus workgroups return).
 constexpr int kRunsLds = 1024;   // tile bases kept in LDS (more runs: read from memory)
 static_assert(sizeof(IndexRun) % 8 == 0, "run descriptor copied as 8-byte words");
 
