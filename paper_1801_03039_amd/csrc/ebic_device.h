@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+constexpr int kAlignedThreads = 320;   // largest single-run whole-candidate workgroup
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -157,7 +158,8 @@ __device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)
 //     last share writes the result (finish_part).  Shared by the single-run
 //     kernel and the persistent multi-run kernel.
 //   ALIGNED = true: the workgroup holds `cpw` whole candidates (requires
-//     ceil(W / V) <= kBlock); counts are summed with LDS atomics and the
+//     ceil(W / V) <= kBlock and cpw <= kBlock; the workgroup may have up to
+//     kAlignedThreads lanes); counts are summed with LDS atomics and the
 //     first lane of each candidate writes its result after a workgroup
 //     barrier -- no global atomics and no accumulator scratch.
 template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES = true, bool OFF32 = false>

@@ -98,16 +98,18 @@ def test_long_series_beyond_lds_stage(ebic, path):
         _check(ebic, a, pop, path, sigma=10, k=k, neg=True)
 
 
-@pytest.mark.parametrize("n", [8192, 8193, 20480, 20481, 32768, 32769, 65536, 65537])
+@pytest.mark.parametrize("n", [1, 64, 200, 5000, 8192, 8193, 10000, 15000, 20000, 20480, 20481,
+                               32768, 32769, 65536, 65537])
 def test_tiling_boundary_row_counts(ebic, n):
     # The index evaluator holds whole candidates per workgroup with 1, 2 or
     # 4 words per lane up to 8192, 20480 and 65536 rows, and spreads taller
     # matrices over workgroups; both sides of each switch (and of 32768
-    # rows), with planted rows.
+    # rows), and heights that pack 1 to 64 candidates per workgroup, with
+    # planted rows.
     rng = np.random.default_rng(n)
     m = 24
     a = rng.standard_normal((n, m)).astype(np.float32)
-    rows = rng.choice(n, size=300, replace=False)
+    rows = rng.choice(n, size=min(300, n), replace=False)
     order = rng.permutation(m)[:8]
     a[np.ix_(rows, order)] = np.sort(a[np.ix_(rows, order)], axis=1)
     pop = synth.random_population(rng, m, 150, 2, 10) + [list(order), list(order[:5])]
