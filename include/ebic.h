@@ -507,9 +507,9 @@ ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *c
  * Every kept child is scored exactly on the GPU; only kept children enter
  * the tabu list.  The model is trained each generation (train_steps Adam
  * steps) on the exact (candidate, log(1 + fitness)) pairs of the last
- * replay_generations generations.  The judge of the ranking: in a screened
- * generation, judge_sample pool members drawn uniformly (from a stream of
- * the judge's own) are also scored exactly and compared with the model's
+ * replay_generations generations.  The rank check: in a screened
+ * generation, check_sample pool members drawn uniformly (from a stream of
+ * the check's own) are also scored exactly and compared with the model's
  * predictions (Spearman rank correlation); in a plainly bred generation the
  * new members are.  A generation is screened only if the previous
  * generation's correlation reached min_rank_corr, otherwise it is bred
@@ -531,7 +531,7 @@ typedef struct {
     ebic_mlp_config mlp;          /* ebic_mlp_defaults with lr 3e-3 */
     ebic_surrogate_fn on_surrogate;
     void *user;
-    int32_t judge_sample;         /* 512: pool members scored exactly to judge the ranking */
+    int32_t check_sample;         /* 512: pool members scored exactly to check the ranking */
     int32_t exact_rerank;         /* 0; r > 0: the network keeps r x (P - elites) of the
                                      pool, those are scored exactly and the best kept */
 } ebic_surrogate_params;

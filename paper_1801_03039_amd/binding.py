@@ -914,7 +914,7 @@ class SurrogateParamsC(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("oversample", _i32), ("warmup_generations", _i32),
                 ("train_steps", _i32), ("replay_generations", _i32), ("min_rank_corr", _dbl),
                 ("mlp_seed", _u64), ("mlp", MlpConfig), ("on_surrogate", SURROGATE_FN),
-                ("user", _vp), ("judge_sample", _i32), ("exact_rerank", _i32)]
+                ("user", _vp), ("check_sample", _i32), ("exact_rerank", _i32)]
 
 
 _surrogate_defaults = _sig("ebic_surrogate_defaults", None, [_P(SurrogateParamsC)])
@@ -928,12 +928,12 @@ def evolve_surrogate(ctx: Context, seed: int, generations: int, cfg: EvolveConfi
                      on_surrogate: Optional[Callable[[dict], None]] = None, **surrogate) -> EvolveResult:
     """Surrogate-screened EBIC run (``ebic_evolve_surrogate``).  Keyword
     arguments override ebic_surrogate_defaults: oversample, warmup_generations,
-    train_steps, replay_generations, min_rank_corr, mlp_seed, judge_sample,
+    train_steps, replay_generations, min_rank_corr, mlp_seed, check_sample,
     exact_rerank, lr, hidden, embed_dim."""
     sp = SurrogateParamsC()
     _surrogate_defaults(ctypes.byref(sp))
     for k in ("oversample", "warmup_generations", "train_steps", "replay_generations",
-              "min_rank_corr", "mlp_seed", "judge_sample", "exact_rerank"):
+              "min_rank_corr", "mlp_seed", "check_sample", "exact_rerank"):
         if k in surrogate:
             setattr(sp, k, surrogate.pop(k))
     for k in ("lr", "hidden", "embed_dim"):

@@ -257,7 +257,7 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
         };
         // The lane of the first word validates every column (batched,
         // branch-free reads; skipped when staging found every staged column
-        // in range) and reports the verdict with its part; other lanes only
+        // in range) and reports the outcome with its part; other lanes only
         // clamp column indices so that no read leaves the index.
         if (active && g == 0) bad = !ok_range;
         if (active && g == 0 && (!kLds || staged_bad)) {

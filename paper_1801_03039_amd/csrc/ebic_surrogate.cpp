@@ -79,7 +79,7 @@ void ebic_surrogate_defaults(ebic_surrogate_params *s) {
     s->train_steps = 16;
     s->replay_generations = 4;
     s->min_rank_corr = 0.1;
-    s->judge_sample = 512;
+    s->check_sample = 512;
     s->exact_rerank = 0;
     s->mlp_seed = 0x5EED;
     ebic_mlp_defaults(&s->mlp);
@@ -119,8 +119,8 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
     double last_corr = -1.0;
     bool have_corr = false;
     ebic_status score_st = EBIC_OK;
-    // The judge's own stream (the run's stream is not touched).
-    SplitMix64 judge_rng(seed ^ 0xA5A5A5A5D1B54A32ull);
+    // The rank check's own stream (the run's stream is not touched).
+    SplitMix64 check_rng(seed ^ 0xA5A5A5A5D1B54A32ull);
     std::vector<int32_t> pool_off, pool_cols;   // the last screened pool
     std::vector<float> pool_pred;
 
@@ -182,7 +182,7 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
         rebase(pop, first, off, cols);
         // The model's view of the new members before their exact scores.
         double corr = 0.0;
-        bool judged = false;
+        bool checked = false;
         if (gen > 0 && n > 0) {
             pred.assign((size_t)n, 0.f);
             if ((st = ebic_mlp_predict(net, off.data(), cols.data(), n, pred.data())) != EBIC_OK)
@@ -196,15 +196,15 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
             return st;
         eval_ms += ms_since(e0);
         evaluated += n;
-        if (screen && pool > 0 && sp->judge_sample > 0) {
+        if (screen && pool > 0 && sp->check_sample > 0) {
             // Judge on a uniform sample of the whole pool, scored exactly: the
             // admitted children alone are a truncated sample whose rank
             // correlation says little about the ranking of the pool.
-            const int32_t S = std::min(sp->judge_sample, pool);
+            const int32_t S = std::min(sp->check_sample, pool);
             std::vector<int32_t> pick((size_t)pool);
             for (int32_t i = 0; i < pool; ++i) pick[(size_t)i] = i;
             for (int32_t i = 0; i < S; ++i) {        // partial Fisher-Yates
-                const int32_t j = i + (int32_t)judge_rng.below((uint64_t)(pool - i));
+                const int32_t j = i + (int32_t)check_rng.below((uint64_t)(pool - i));
                 std::swap(pick[(size_t)i], pick[(size_t)j]);
             }
             std::vector<int32_t> so(1, 0), sc, scnt((size_t)S);
@@ -223,11 +223,11 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
             eval_ms += ms_since(j0);
             evaluated += S;
             corr = spearman(spd, sfit);
-            judged = true;
+            checked = true;
         } else if (gen > 0 && n > 0) {
             std::vector<double> pd(pred.begin(), pred.end());
             corr = spearman(pd, fit);
-            judged = true;
+            checked = true;
         }
         run.accept(cnt.data(), fit.data());
         // Train on the exact pairs of the latest generations.
@@ -252,12 +252,12 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
                 return st;
             loss = l;
         }
-        if (judged) {
+        if (checked) {
             last_corr = corr;
             have_corr = true;
         }
         if (sp->on_surrogate)
-            sp->on_surrogate(sp->user, gen, screen ? 1 : 0, judged ? corr : NAN, loss, pool);
+            sp->on_surrogate(sp->user, gen, screen ? 1 : 0, checked ? corr : NAN, loss, pool);
     }
 
     // Steps 6-7 with the expansion parameters.

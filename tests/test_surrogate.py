@@ -169,7 +169,7 @@ def test_exact_oversampled_run_matches_its_host_definition(E, small):
 
 def test_two_stage_screen_admits_exactly_scored_children(E, small):
     # network halves the pool, exact scores rank the rest: admitted children
-    # equal the oracle and the pool judge reports a correlation
+    # equal the oracle and the pool rank check reports a correlation
     w, a, _ = small
     gens, info = [], []
     with E.Context(a) as ctx:
