@@ -210,7 +210,10 @@ def test_replays_keep_state(E, mats):
             _check_runs(mats, pops2, got, 3, 1, True)
 
 
-def test_batch_evolve_matches_oracle_runs(E):
+@pytest.mark.parametrize("shape", [None, (-1, 2, 8, 1, 1), (0, 4, 2, 0, 1)])
+def test_batch_evolve_matches_oracle_runs(E, shape):
+    # tuned on the first generation (None), or a fixed shape replayed as a
+    # graph whose queue-free grid grows with the largest generation seen
     rng = np.random.default_rng(4)
     shapes = [(150, 20), (300, 12), (90, 30), (500, 8)]
     mats_ = [rng.standard_normal(s).astype(np.float32) for s in shapes]
@@ -220,7 +223,9 @@ def test_batch_evolve_matches_oracle_runs(E):
                          expand=E.Trend(8, 1, True))
     gens = {r: [] for r in range(len(mats_))}
     with E.Batch(mats_) as b:
-        _note("batch evolve")
+        _note(f"batch evolve shape={shape}")
+        if shape is not None:
+            b.set_tuning(*shape)
         res = b.evolve(seeds, G, cfg, on_generation=lambda r, g: gens[r].append(g), host_threads=3)
     for r, (a, s) in enumerate(zip(mats_, seeds)):
         op = oev.EvolveParams(population=60, len_min=3, len_max=7, eval=oev.TrendParams(8),
