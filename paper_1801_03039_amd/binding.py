@@ -747,31 +747,37 @@ class Batch:
         Returns one dict (counts, fitness[, masks]) per run (None if skipped)."""
         R = len(self.n_rows)
         assert len(pops) == R
-        offs, cls, Ps, cnts, fits, msks = [], [], [], [], [], []
+        offs, cls, Ps, msks = [], [], [], []
         for r in range(R):
             if pops[r] is None or len(pops[r][0]) <= 1:
-                offs.append(None); cls.append(None); Ps.append(0)
-                cnts.append(None); fits.append(None); msks.append(None)
+                offs.append(None); cls.append(None); Ps.append(0); msks.append(None)
                 continue
             o = np.ascontiguousarray(pops[r][0], dtype=np.int32)
             c = np.ascontiguousarray(pops[r][1], dtype=np.int32)
-            P = len(o) - 1
-            offs.append(o); cls.append(c); Ps.append(P)
-            cnts.append(np.zeros(P, dtype=np.int32)); fits.append(np.zeros(P, dtype=np.float64))
-            msks.append(np.zeros((P, 2, mask_words(self.n_rows[r])), dtype=np.uint64)
+            offs.append(o); cls.append(c); Ps.append(len(o) - 1)
+            msks.append(np.zeros((len(o) - 1, 2, mask_words(self.n_rows[r])), dtype=np.uint64)
                         if want_masks else None)
         P_arr = np.array(Ps, dtype=np.int32)
+        # one allocation per output; run r's results are a slice of it
+        base = np.zeros(R + 1, dtype=np.int64)
+        np.cumsum(P_arr, out=base[1:])
+        counts = np.empty(int(base[-1]), dtype=np.int32)
+        fitness = np.empty(int(base[-1]), dtype=np.float64)
+        cnt_p = (ctypes.c_void_p * R).from_buffer_copy(
+            (counts.ctypes.data + 4 * base[:-1]).astype(np.uint64).tobytes())
+        fit_p = (ctypes.c_void_p * R).from_buffer_copy(
+            (fitness.ctypes.data + 8 * base[:-1]).astype(np.uint64).tobytes())
         prm = make_params(sigma, max_violations, negative_trends, want_masks)
         _check(_batch_evaluate(self._h, _ptr_array(offs, None), _ptr_array(cls, None),
                                P_arr.ctypes.data, ctypes.byref(prm),
                                _ptr_array(msks, None) if want_masks else None,
-                               _ptr_array(cnts, None), _ptr_array(fits, None), int(bool(tune))))
+                               cnt_p, fit_p, int(bool(tune))))
         out = []
         for r in range(R):
             if Ps[r] == 0:
                 out.append(None)
                 continue
-            d = {"counts": cnts[r], "fitness": fits[r]}
+            d = {"counts": counts[base[r]:base[r + 1]], "fitness": fitness[base[r]:base[r + 1]]}
             if want_masks:
                 d["masks"] = msks[r]
             out.append(d)

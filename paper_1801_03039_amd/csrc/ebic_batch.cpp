@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -63,6 +64,11 @@ struct ebic_batch {
 };
 
 namespace {
+
+// Host-array calls check and pack the runs' columns on up to kPackThreads
+// threads once they hold kPackParallelCols columns or more.
+constexpr int32_t kPackThreads = 8;
+constexpr int64_t kPackParallelCols = int64_t(1) << 17;
 
 ebic_status bfail(ebic_status st, const std::string &msg) {
     set_thread_error(msg.c_str());
@@ -513,34 +519,74 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
     q.params = params;
     q.masks = params->want_masks != 0;
     q.P.assign((size_t)R, 0);
+    std::vector<int64_t> cand_base((size_t)R, 0), col_base((size_t)R, 0);
     int64_t n_cols = 0, n_mask = 0;
+    // Pass 1: counts, pointers and offsets (which size the staging buffers).
     for (int32_t r = 0; r < R; ++r) {
         if (P[r] < 0) return bfail(EBIC_E_ARG, "P must be >= 0");
         if (P[r] == 0) continue;
         ebic_ctx *c = b->ctx[(size_t)r];
         if (!offsets[r] || !cols[r] || !counts[r] || !fitness[r] || (q.masks && !masks[r]))
             return bfail(EBIC_E_ARG, "null per-run array");
-        ebic_status st;
-        if (!valid_cbf(c, offsets[r], cols[r], P[r], &st)) {
-            set_thread_error(("run " + std::to_string(r) + ": " + c->err).c_str());
-            return st;
-        }
+        const int32_t *o = offsets[r];
+        if (o[0] != 0)
+            return bfail(EBIC_E_ARG, "run " + std::to_string(r) + ": offsets[0] must be 0");
+        for (int32_t i = 0; i < P[r]; ++i)
+            if (o[i + 1] <= o[i])
+                return bfail(EBIC_E_ARG, "run " + std::to_string(r) +
+                                             ": offsets must increase (every series has L >= 1); "
+                                             "candidate " + std::to_string(i));
         if ((int64_t)P[r] * c->W > (int64_t(1) << 32) - 256)
             return bfail(EBIC_E_ARG, "population too large for one launch");
         q.P[(size_t)r] = P[r];
+        cand_base[(size_t)r] = q.n_cand;
+        col_base[(size_t)r] = n_cols;
         q.n_cand += P[r];
-        n_cols += offsets[r][P[r]];
+        n_cols += o[P[r]];
         if (q.masks) n_mask += (int64_t)P[r] * 2 * c->W;
     }
+    if (n_cols > INT32_MAX || q.n_cand > INT32_MAX)
+        return bfail(EBIC_E_ARG, "batched populations hold more than 2^31 - 1 columns; split them");
     q.n_cols = n_cols;
     if (q.n_cand == 0) return EBIC_OK;
     BHIP(hipSetDevice(b->device));
     ebic_status st = reserve(b, q.n_cand, n_cols, n_mask);
     if (st != EBIC_OK) return st;
-    Packer pk{b};
-    b->h_off[0] = 0;
+    // Pass 2: every run's columns checked (range, distinct within a series)
+    // and packed into the staging buffers in one pass, runs spread over host
+    // threads when there is enough to share; the first failing run (in run
+    // order) is reported.
+    std::vector<ebic_status> run_st((size_t)R, EBIC_OK);
+    auto pack = [&](int32_t r) {
+        if (!q.P[(size_t)r]) return;
+        ebic_status s = EBIC_OK;
+        if (!pack_valid_cbf(b->ctx[(size_t)r], offsets[r], cols[r], q.P[(size_t)r],
+                            (int32_t)col_base[(size_t)r], b->h_off + cand_base[(size_t)r],
+                            b->h_cols + col_base[(size_t)r], &s))
+            run_st[(size_t)r] = s;
+    };
+    const int32_t threads =
+        n_cols < kPackParallelCols
+            ? 1
+            : std::min<int32_t>({R, kPackThreads,
+                                 (int32_t)std::max(1u, std::thread::hardware_concurrency())});
+    if (threads <= 1) {
+        for (int32_t r = 0; r < R; ++r) pack(r);
+    } else {
+        std::atomic<int32_t> next{0};
+        std::vector<std::thread> pool;
+        for (int32_t t = 0; t < threads; ++t)
+            pool.emplace_back([&] {
+                for (int32_t r; (r = next.fetch_add(1)) < R;) pack(r);
+            });
+        for (std::thread &th : pool) th.join();
+    }
     for (int32_t r = 0; r < R; ++r)
-        if (q.P[(size_t)r]) pk.add(offsets[r], cols[r], q.P[(size_t)r]);
+        if (run_st[(size_t)r] != EBIC_OK) {
+            set_thread_error(("run " + std::to_string(r) + ": " + b->ctx[(size_t)r]->err).c_str());
+            return run_st[(size_t)r];
+        }
+    b->h_off[q.n_cand] = (int32_t)n_cols;
     if (tune_now && (st = tune(b, q)) != EBIC_OK) return st;
     if ((st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
     int64_t cand = 0, mw = 0;

@@ -96,6 +96,10 @@ void set_thread_error(const char *msg);
 ebic_status ensure_index(ebic_ctx *ctx);  // builds the order index if missing
 bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
                ebic_status *st);          // host CBF checks of ebic_evaluate
+// The same checks, copying the columns to dst_cols (column i of the CBF to
+// dst_cols[i]) and dst_off[c] = col_base + offsets[c] for c < P in one pass.
+bool pack_valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
+                    int32_t col_base, int32_t *dst_off, int32_t *dst_cols, ebic_status *st);
 
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               const EvalArgs &e, hipStream_t stream);

@@ -236,8 +236,12 @@ ebic_status create_common(const float *a, bool on_device, int64_t n_rows, int32_
     return EBIC_OK;
 }
 
+// Host CBF checks: offsets[0] = 0, increasing offsets, columns in range and
+// distinct within a series.  With dst_cols, the columns are also copied to
+// dst_cols and dst_off[c] = col_base + offsets[c] for c < P, in the same pass.
 bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
-               ebic_status *st) {
+               ebic_status *st, int32_t *dst_off = nullptr, int32_t *dst_cols = nullptr,
+               int32_t col_base = 0) {
     if (offsets[0] != 0) {
         *st = fail(ctx, EBIC_E_ARG, "offsets[0] must be 0");
         return false;
@@ -249,6 +253,7 @@ bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
                                             std::to_string(c));
             return false;
         }
+        if (dst_off) dst_off[c] = col_base + offsets[c];
         for (int32_t i = offsets[c]; i < offsets[c + 1]; ++i) {
             const int32_t col = cols[i];
             if (col < 0 || col >= ctx->m) {
@@ -260,6 +265,7 @@ bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
                 return false;
             }
             seen[(size_t)col] = c;
+            if (dst_cols) dst_cols[i] = col;
         }
     }
     return true;
@@ -273,6 +279,10 @@ ebic_status ensure_index(ebic_ctx *ctx) { return build_index(ctx); }
 bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
                ebic_status *st) {
     return check_cbf(ctx, offsets, cols, P, st);
+}
+bool pack_valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
+                    int32_t col_base, int32_t *dst_off, int32_t *dst_cols, ebic_status *st) {
+    return check_cbf(ctx, offsets, cols, P, st, dst_off, dst_cols, col_base);
 }
 }  // namespace ebic
 

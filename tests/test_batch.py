@@ -191,6 +191,44 @@ def test_batch_errors(E, mats):
             b.time_replays(3)          # the last request launched nothing
 
 
+def test_parallel_packing_results_and_errors(E):
+    # Enough columns for the host-array call to check and pack the runs on
+    # several threads: results equal the oracle, and a malformed run is
+    # reported by its index (the first one in run order).
+    rng = np.random.default_rng(8)
+    mats_ = [rng.standard_normal((int(rng.integers(60, 200)), 30)).astype(np.float32)
+             for _ in range(16)]
+    pops = [synth.pack_cbf(synth.random_population(rng, 30, 1024, 5, 12)) for _ in mats_]
+    assert sum(int(o[-1]) for o, _ in pops) >= 1 << 17
+    with E.Batch(mats_) as b:
+        _note("parallel packing")
+        got = b.evaluate(pops, sigma=3, max_violations=1, negative_trends=True)
+        for i in (0, 7, 15):
+            ref = oracle.evaluate(mats_[i], pops[i][0], pops[i][1], sigma=3, max_violations=1,
+                                  negative_trends=True)
+            assert np.array_equal(got[i]["counts"], ref["counts"])
+            assert np.array_equal(got[i]["fitness"].view(np.int64), ref["fitness"].view(np.int64))
+        bad = list(pops)
+        o11, c11 = pops[11][0], pops[11][1].copy()
+        c11[o11[500] + 1] = c11[o11[500]]                      # a repeated column in run 11
+        o5, c5 = pops[5][0], pops[5][1].copy()
+        c5[o5[3]] = 30                                        # a column out of range in run 5
+        bad[11] = (o11, c11)
+        with pytest.raises(E.EbicError, match="run 11"):
+            b.evaluate(bad, sigma=3)
+        bad[5] = (o5, c5)
+        with pytest.raises(E.EbicError, match="run 5"):
+            b.evaluate(bad, sigma=3)
+        o2 = pops[2][0].copy()
+        o2[10] = o2[9]                                        # an empty series in run 2
+        bad[2] = (o2, pops[2][1])
+        with pytest.raises(E.EbicError, match="run 2"):
+            b.evaluate(bad, sigma=3)
+        again = b.evaluate(pops, sigma=3, max_violations=1, negative_trends=True)
+        for g, h in zip(got, again):
+            assert np.array_equal(g["counts"], h["counts"])
+
+
 def test_replays_keep_state(E, mats):
     # Back-to-back replays of a launch (queue and accumulators left as
     # found) do not disturb later launches, in every tiling mode.
