@@ -370,19 +370,24 @@ struct Packer {
     }
 };
 
+// f(0) .. f(n - 1) on up to `threads` threads; the calling thread takes
+// items too, so the loop drains even if a helper thread cannot be started.
 template <typename F>
 void parallel_for(int32_t n, int32_t threads, F &&f) {
     threads = std::max(1, std::min(threads, n));
-    if (threads == 1) {
-        for (int32_t i = 0; i < n; ++i) f(i);
-        return;
-    }
     std::atomic<int32_t> next{0};
+    auto drain = [&] {
+        for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
+    };
     std::vector<std::thread> pool;
-    for (int32_t t = 0; t < threads; ++t)
-        pool.emplace_back([&] {
-            for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
-        });
+    for (int32_t t = 1; t < threads; ++t) {
+        try {
+            pool.emplace_back(drain);
+        } catch (...) {
+            break;
+        }
+    }
+    drain();
     for (auto &th : pool) th.join();
 }
 
@@ -570,17 +575,7 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
             ? 1
             : std::min<int32_t>({R, kPackThreads,
                                  (int32_t)std::max(1u, std::thread::hardware_concurrency())});
-    if (threads <= 1) {
-        for (int32_t r = 0; r < R; ++r) pack(r);
-    } else {
-        std::atomic<int32_t> next{0};
-        std::vector<std::thread> pool;
-        for (int32_t t = 0; t < threads; ++t)
-            pool.emplace_back([&] {
-                for (int32_t r; (r = next.fetch_add(1)) < R;) pack(r);
-            });
-        for (std::thread &th : pool) th.join();
-    }
+    parallel_for(R, threads, pack);
     for (int32_t r = 0; r < R; ++r)
         if (run_st[(size_t)r] != EBIC_OK) {
             set_thread_error(("run " + std::to_string(r) + ": " + b->ctx[(size_t)r]->err).c_str());

@@ -820,17 +820,22 @@ class Run {
     template <typename F>
     static void run_shares(int32_t n, int32_t threads, F &&f) {
         if (threads <= 0) threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
-        threads = std::min(threads, n);
-        if (threads <= 1) {
-            for (int32_t i = 0; i < n; ++i) f(i);
-            return;
-        }
+        threads = std::max(1, std::min(threads, n));
+        // the calling thread takes shares too, so the loop drains even if a
+        // helper thread cannot be started
         std::atomic<int32_t> next{0};
+        auto drain = [&] {
+            for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
+        };
         std::vector<std::thread> pool;
-        for (int32_t t = 0; t < threads; ++t)
-            pool.emplace_back([&] {
-                for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
-            });
+        for (int32_t t = 1; t < threads; ++t) {
+            try {
+                pool.emplace_back(drain);
+            } catch (...) {
+                break;
+            }
+        }
+        drain();
         for (std::thread &th : pool) th.join();
     }
 
