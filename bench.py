@@ -648,7 +648,7 @@ def main():
                                 tournament=w.tournament)
         log(f"EBIC run, {G} generations")
         t0 = time.perf_counter()
-        res = ebic.evolve(ctx, w.seed, G, cfg, on_generation=on_gen)
+        res = ebic.evolve(ctx, w.seed, G, cfg, on_generation=on_gen, report_generations=keep)
         run_ms = (time.perf_counter() - t0) * 1e3
         st = res.stats
         gens = max(st["generations_run"], 1)

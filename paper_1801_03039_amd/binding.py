@@ -345,11 +345,15 @@ def _params_c(cfg: EvolveConfig, on_gen) -> EvolveParamsC:
     return p
 
 
-def _gen_callback(fn: Optional[Callable[[Generation], None]]):
+def _gen_callback(fn: Optional[Callable[[Generation], None]], only=None):
+    """The C callback for ``fn``; with ``only`` (a set of generation
+    numbers), other generations return at once without copying anything."""
     if fn is None:
         return GENERATION_FN()
 
     def cb(user, gen, off, cols, P, counts, fit):
+        if only is not None and gen not in only:
+            return
         o = np.ctypeslib.as_array(off, shape=(P + 1,)).copy()
         n = int(o[-1])
         c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
@@ -387,9 +391,12 @@ def _finish(res_ptr, n_rows: int) -> EvolveResult:
 
 
 def evolve(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
-           on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
-    """EBIC run (Steps 1-7) on the GPU context ``ctx``."""
-    cb = _gen_callback(on_generation)
+           on_generation: Optional[Callable[[Generation], None]] = None,
+           report_generations=None) -> EvolveResult:
+    """EBIC run (Steps 1-7) on the GPU context ``ctx``.  ``on_generation``
+    receives every generation, or only those in ``report_generations``."""
+    cb = _gen_callback(on_generation,
+                       None if report_generations is None else set(report_generations))
     p = _params_c(cfg, cb)
     res = _vp()
     st = _evolve(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations), ctypes.byref(p),

@@ -97,3 +97,25 @@ def test_checkpointed_gpu_run_equals_evolve(E):
     assert [b["cols"] for b in res.biclusters] == [b["cols"] for b in ref.biclusters]
     for b, c in zip(res.biclusters, ref.biclusters):
         assert np.array_equal(b["mask_words"], c["mask_words"])
+
+
+def test_reported_generations_subset(E):
+    # on_generation restricted to some generations sees exactly those, equal
+    # to the same generations of a fully reported run with the same seed
+    w = synth.WORKLOADS["tiny"]
+    a, _ = synth.make_matrix(w)
+    cfg = E.EvolveConfig(population=w.population, len_min=w.len_min, len_max=w.len_max,
+                         eval=E.Trend(w.sigma, w.max_violations, w.negative_trends),
+                         expand=E.Trend(w.sigma, w.max_violations, True))
+    full, part = [], []
+    with E.Context(a) as ctx:
+        _note("reported generations subset")
+        r1 = E.evolve(ctx, 5, 12, cfg, on_generation=full.append)
+        r2 = E.evolve(ctx, 5, 12, cfg, on_generation=part.append, report_generations={0, 4, 12})
+    assert [g.gen for g in part] == [0, 4, 12]
+    by_gen = {g.gen: g for g in full}
+    for g in part:
+        h = by_gen[g.gen]
+        assert g.population == h.population
+        assert np.array_equal(g.fitness.view(np.int64), h.fitness.view(np.int64))
+    assert [b["cols"] for b in r1.biclusters] == [b["cols"] for b in r2.biclusters]
