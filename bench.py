@@ -386,9 +386,9 @@ def run_surrogate(args):
         trace = []
         t0 = time.perf_counter()
 
-        def on_gen(g):
-            trace.append((time.perf_counter() - t0, float(g.fitness.max(initial=0.0))))
-        res = fn(on_generation=on_gen, **kw)
+        def on_best(gen, best):
+            trace.append((time.perf_counter() - t0, best))
+        res = fn(on_best=on_best, **kw)
         return res, trace, time.perf_counter() - t0
 
     def first_reach(trace, target):

@@ -345,6 +345,21 @@ def _params_c(cfg: EvolveConfig, on_gen) -> EvolveParamsC:
     return p
 
 
+def _best_callback(fn: Callable[[int, float], None]):
+    """The C callback reporting (generation, best fitness of the scored
+    population) without copying the population."""
+    def cb(user, gen, off, cols, P, counts, fit):
+        f = np.ctypeslib.as_array(fit, shape=(max(P, 1),))[:P]
+        fn(int(gen), float(f.max(initial=0.0)))
+    return GENERATION_FN(cb)
+
+
+def _run_callback(on_generation, on_best, only=None):
+    if on_generation is not None and on_best is not None:
+        raise ValueError("give on_generation or on_best, not both")
+    return _best_callback(on_best) if on_best is not None else _gen_callback(on_generation, only)
+
+
 def _gen_callback(fn: Optional[Callable[[Generation], None]], only=None):
     """The C callback for ``fn``; with ``only`` (a set of generation
     numbers), other generations return at once without copying anything."""
@@ -392,10 +407,12 @@ def _finish(res_ptr, n_rows: int) -> EvolveResult:
 
 def evolve(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
            on_generation: Optional[Callable[[Generation], None]] = None,
-           report_generations=None) -> EvolveResult:
+           report_generations=None,
+           on_best: Optional[Callable[[int, float], None]] = None) -> EvolveResult:
     """EBIC run (Steps 1-7) on the GPU context ``ctx``.  ``on_generation``
-    receives every generation, or only those in ``report_generations``."""
-    cb = _gen_callback(on_generation,
+    receives every generation, or only those in ``report_generations``;
+    ``on_best(generation, best fitness)`` is a lighter alternative."""
+    cb = _run_callback(on_generation, on_best,
                        None if report_generations is None else set(report_generations))
     p = _params_c(cfg, cb)
     res = _vp()
@@ -515,9 +532,10 @@ EXPORTED += ["ebic_evolve_oversampled"]
 
 def evolve_oversampled(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
                        oversample: int = 8, warmup_generations: int = 3,
-                       on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
+                       on_generation: Optional[Callable[[Generation], None]] = None,
+                       on_best: Optional[Callable[[int, float], None]] = None) -> EvolveResult:
     """Offspring screening by exact GPU fitness (``ebic_evolve_oversampled``)."""
-    cb = _gen_callback(on_generation)
+    cb = _run_callback(on_generation, on_best)
     p = _params_c(cfg, cb)
     res = _vp()
     st = _evolve_oversampled(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations),
@@ -938,7 +956,9 @@ EXPORTED += ["ebic_surrogate_defaults", "ebic_evolve_surrogate"]
 
 def evolve_surrogate(ctx: Context, seed: int, generations: int, cfg: EvolveConfig,
                      on_generation: Optional[Callable[[Generation], None]] = None,
-                     on_surrogate: Optional[Callable[[dict], None]] = None, **surrogate) -> EvolveResult:
+                     on_surrogate: Optional[Callable[[dict], None]] = None,
+                     on_best: Optional[Callable[[int, float], None]] = None,
+                     **surrogate) -> EvolveResult:
     """Surrogate-screened EBIC run (``ebic_evolve_surrogate``).  Keyword
     arguments override ebic_surrogate_defaults: oversample, warmup_generations,
     train_steps, replay_generations, min_rank_corr, mlp_seed, check_sample,
@@ -962,7 +982,7 @@ def evolve_surrogate(ctx: Context, seed: int, generations: int, cfg: EvolveConfi
                           "loss": float(loss), "pool": int(pool)})
         scb = SURROGATE_FN(_s)
     sp.on_surrogate = scb
-    gcb = _gen_callback(on_generation)
+    gcb = _run_callback(on_generation, on_best)
     p = _params_c(cfg, gcb)
     res = _vp()
     st = _evolve_surrogate(ctx.handle, int(seed) & ((1 << 64) - 1), int(generations),

@@ -119,3 +119,21 @@ def test_reported_generations_subset(E):
         assert g.population == h.population
         assert np.array_equal(g.fitness.view(np.int64), h.fitness.view(np.int64))
     assert [b["cols"] for b in r1.biclusters] == [b["cols"] for b in r2.biclusters]
+
+
+def test_best_fitness_callback(E):
+    # on_best reports each generation's best fitness, as the full callback sees it
+    w = synth.WORKLOADS["tiny"]
+    a, _ = synth.make_matrix(w)
+    cfg = E.EvolveConfig(population=w.population, len_min=w.len_min, len_max=w.len_max,
+                         eval=E.Trend(w.sigma, w.max_violations, w.negative_trends),
+                         expand=E.Trend(w.sigma, w.max_violations, True))
+    full, best = [], []
+    with E.Context(a) as ctx:
+        _note("best-fitness callback")
+        E.evolve(ctx, 9, 8, cfg, on_generation=full.append)
+        E.evolve(ctx, 9, 8, cfg, on_best=lambda g, f: best.append((g, f)))
+        with pytest.raises(ValueError):
+            E.evolve(ctx, 9, 2, cfg, on_generation=full.append, on_best=print)
+    assert [g for g, _ in best] == [g.gen for g in full]
+    assert [f for _, f in best] == [float(g.fitness.max(initial=0.0)) for g in full]
