@@ -149,6 +149,24 @@ __device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)
     }
 }
 
+// Calls f(integral_constant<int, r>) for the run-time count r in [1, N]
+// (nothing for r = 0): the last, shorter batch of a series' pairs.
+template <int N>
+struct ShortBatch {
+    template <class F>
+    __device__ __forceinline__ static void run(int32_t r, F &&f) {
+        if (r == N)
+            f(std::integral_constant<int, N>{});
+        else
+            ShortBatch<N - 1>::run(r, f);
+    }
+};
+template <>
+struct ShortBatch<0> {
+    template <class F>
+    __device__ __forceinline__ static void run(int32_t, F &&) {}
+};
+
 // One tile of one run.  An item is a candidate and V consecutive 64-row
 // words of it (V words per lane share the lane's column reads and loop).
 // Two tilings:
@@ -162,7 +180,8 @@ __device__ __forceinline__ void load_words(global_ptr<uint64_t> p, uint64_t (&o)
 //     kAlignedThreads lanes); counts are summed with LDS atomics and the
 //     first lane of each candidate writes its result after a workgroup
 //     barrier -- no global atomics and no accumulator scratch.
-template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES = true, bool OFF32 = false>
+template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES = true, bool OFF32 = false,
+          bool TAIL = false>
 __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uint32_t cpw,
                                            const int32_t *__restrict__ offsets,
                                            const int32_t *__restrict__ cols, int64_t n_entries,
@@ -282,64 +301,125 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                 return idx + w0 + pq * wpad;
             }
         };
-        const int32_t last = L - 1;
-        int32_t p = col(0);
-        p = (p < 0 || p >= m) ? 0 : p;
-        for (int32_t t = 1; t < L; t += U) {
-            // Column reads and order-word loads of the batch are issued
-            // unconditionally (indices past the end repeat the last column,
-            // a harmless in-bounds read whose words are then ignored).
-            int32_t q[U];
+        if constexpr (TAIL) {
+            int32_t p = col(0);
+            p = (p < 0 || p >= m) ? 0 : p;
+            // One batch of N consecutive pairs from pair t (t + N <= L): the
+            // column reads and order-word loads are all issued before any is
+            // consumed.  Returns whether a row of the lane's words is still
+            // undecided.
+            auto batch = [&](auto n, int32_t t) -> bool {
+                constexpr int N = decltype(n)::value;
+                int32_t q[N];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t x = col(min(t + u, last));
-                q[u] = (x < 0 || x >= m) ? 0 : x;
-            }
-            uint64_t lu[U][V], ld[U][V];
-            uint8_t tf[U];
-            int32_t pp = p;
+                for (int u = 0; u < N; ++u) {
+                    const int32_t x = col(t + u);
+                    q[u] = (x < 0 || x >= m) ? 0 : x;
+                }
+                uint64_t lu[N][V], ld[N][V];
+                uint8_t tf[N];
+                int32_t pp = p;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t pq = (int64_t)pp * m + q[u];
-                load_words<V>(words_at(pq), lu[u]);
-                if (NEG) tf[u] = TIES ? tie[pq] : 0;
-                pp = q[u];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool in = t + u < L;
-#pragma unroll
-                for (int v = 0; v < V; ++v) lu[u][v] = in ? lu[u][v] : ~0ull;
-                if (NEG) tf[u] = in ? tf[u] : 0;
-            }
-            if (NEG) {
-                // lt(q,p) is the complement of lt(p,q) unless the pair ties;
-                // slots past the end of the series break nothing.
-                pp = p;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (TIES && tf[u]) {
-                        load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
-                    }
-#pragma unroll
-                    for (int v = 0; v < V; ++v) ld[u][v] = t + u < L ? ld[u][v] : ~0ull;
+                for (int u = 0; u < N; ++u) {
+                    const int64_t pq = (int64_t)pp * m + q[u];
+                    load_words<V>(words_at(pq), lu[u]);
+                    if (NEG) tf[u] = TIES ? tie[pq] : 0;
                     pp = q[u];
                 }
-            }
+                if (NEG) {
+                    // lt(q,p) is the complement of lt(p,q) unless the pair ties
+                    pp = p;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+                    for (int u = 0; u < N; ++u) {
+                        if (TIES && tf[u]) {
+                            load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
+                        }
+                        pp = q[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < N; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        fold<K, NEG>(cu[v], cd[v], lu[u][v], NEG ? ld[u][v] : 0ull);
+                p = q[N - 1];
+                uint64_t live = 0;
 #pragma unroll
                 for (int v = 0; v < V; ++v)
-                    fold<K, NEG>(cu[v], cd[v], lu[u][v], NEG ? ld[u][v] : 0ull);
-            p = pp;
-            uint64_t live = 0;
+                    live |= valid[v] & ~(NEG ? (cu[v][K] & cd[v][K]) : cu[v][K]);
+                return live != 0ull;
+            };
+            // Whole batches of U pairs, then the last L - t < U pairs as one
+            // shorter batch: no load reads past the end of the series.
+            int32_t t = 1;
+            bool undecided = true;
+            for (; t + U <= L; t += U)
+                if (!(undecided = batch(std::integral_constant<int, U>{}, t))) break;
+            if (undecided)
+                ShortBatch<U - 1>::run(L - t, [&](auto n) { (void)batch(n, t); });
+        } else {
+            const int32_t last = L - 1;
+            int32_t p = col(0);
+            p = (p < 0 || p >= m) ? 0 : p;
+            for (int32_t t = 1; t < L; t += U) {
+                // Column reads and order-word loads of the batch are issued
+                // unconditionally (indices past the end repeat the last column,
+                // a harmless in-bounds read whose words are then ignored).
+                int32_t q[U];
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                live |= valid[v] & ~(NEG ? (cu[v][K] & cd[v][K]) : cu[v][K]);
-            if (live == 0ull) break;
+                for (int u = 0; u < U; ++u) {
+                    const int32_t x = col(min(t + u, last));
+                    q[u] = (x < 0 || x >= m) ? 0 : x;
+                }
+                uint64_t lu[U][V], ld[U][V];
+                uint8_t tf[U];
+                int32_t pp = p;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t pq = (int64_t)pp * m + q[u];
+                    load_words<V>(words_at(pq), lu[u]);
+                    if (NEG) tf[u] = TIES ? tie[pq] : 0;
+                    pp = q[u];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool in = t + u < L;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) lu[u][v] = in ? lu[u][v] : ~0ull;
+                    if (NEG) tf[u] = in ? tf[u] : 0;
+                }
+                if (NEG) {
+                    // lt(q,p) is the complement of lt(p,q) unless the pair ties;
+                    // slots past the end of the series break nothing.
+                    pp = p;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (TIES && tf[u]) {
+                            load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
+                        }
+#pragma unroll
+                        for (int v = 0; v < V; ++v) ld[u][v] = t + u < L ? ld[u][v] : ~0ull;
+                        pp = q[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        fold<K, NEG>(cu[v], cd[v], lu[u][v], NEG ? ld[u][v] : 0ull);
+                p = pp;
+                uint64_t live = 0;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    live |= valid[v] & ~(NEG ? (cu[v][K] & cd[v][K]) : cu[v][K]);
+                if (live == 0ull) break;
+            }
         }
     };
     if (use_lds)

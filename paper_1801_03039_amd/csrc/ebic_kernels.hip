@@ -209,15 +209,16 @@ __global__ __launch_bounds__(kBlock) void eval_direct_kernel(
     }
 }
 
-template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES, bool OFF32>
+template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES, bool OFF32, bool TAIL>
 __global__ __launch_bounds__(kAlignedThreads) void eval_index_kernel(
     IndexRun R, uint32_t cpw, const int32_t *__restrict__ offsets,
     const int32_t *__restrict__ cols, int64_t n_entries, int32_t sigma,
     uint64_t *__restrict__ masks, unsigned long long *__restrict__ acc,
     int32_t *__restrict__ counts, double *__restrict__ fitness) {
     __shared__ TileLds lds;
-    index_tile<K, NEG, U, V, ALIGNED, TIES, OFF32>(R, blockIdx.x, cpw, offsets, cols, n_entries,
-                                                   sigma, masks, acc, counts, fitness, lds);
+    index_tile<K, NEG, U, V, ALIGNED, TIES, OFF32, TAIL>(R, blockIdx.x, cpw, offsets, cols,
+                                                         n_entries, sigma, masks, acc, counts,
+                                                         fitness, lds);
 }
 
 }  // namespace
@@ -275,32 +276,32 @@ hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m
 // Falling trends read tie flags (and reverse words) only when the matrix
 // has a tied or unordered pair somewhere (`ties`); otherwise lt(q,p) is
 // ~lt(p,q) for every pair and the flags are not loaded.
-template <int K, int U, int V, bool ALIGNED, bool OFF32>
+template <int K, int U, int V, bool ALIGNED, bool OFF32, bool TAIL>
 static void launch_index_o(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 block,
                            const EvalArgs &e, bool ties, hipStream_t stream) {
     if (e.negative && ties)
-        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, true, OFF32>), grid, block,
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, true, OFF32, TAIL>), grid, block,
                            0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
                            e.acc, e.counts, e.fitness);
     else if (e.negative)
-        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, false, OFF32>), grid, block,
+        hipLaunchKernelGGL((eval_index_kernel<K, true, U, V, ALIGNED, false, OFF32, TAIL>), grid, block,
                            0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
                            e.acc, e.counts, e.fitness);
     else
-        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V, ALIGNED, false, OFF32>), grid, block,
+        hipLaunchKernelGGL((eval_index_kernel<K, false, U, V, ALIGNED, false, OFF32, TAIL>), grid, block,
                            0, stream, R, cpw, e.offsets, e.cols, e.n_entries, e.sigma, e.masks,
                            e.acc, e.counts, e.fitness);
 }
 
 // 32-bit index offsets when the whole index is below 4 GiB.
-template <int K, int U, int V, bool ALIGNED>
+template <int K, int U, int V, bool ALIGNED, bool TAIL = false>
 static void launch_index_t(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 block,
                            const EvalArgs &e, bool ties, hipStream_t stream) {
     const uint64_t bytes = (uint64_t)R.m * (uint64_t)R.m * (uint64_t)R.wpad * 8ull;
     if (bytes <= 0xFFFFFFFFull)
-        launch_index_o<K, U, V, ALIGNED, true>(R, cpw, grid, block, e, ties, stream);
+        launch_index_o<K, U, V, ALIGNED, true, TAIL>(R, cpw, grid, block, e, ties, stream);
     else
-        launch_index_o<K, U, V, ALIGNED, false>(R, cpw, grid, block, e, ties, stream);
+        launch_index_o<K, U, V, ALIGNED, false, TAIL>(R, cpw, grid, block, e, ties, stream);
 }
 
 // Whole-candidate workgroups.  With 4 words per lane, as many candidates as
@@ -309,7 +310,7 @@ static void launch_index_t(const IndexRun &R, uint32_t cpw, dim3 grid, dim3 bloc
 // candidates of 157 lanes in 5 waves instead of 1 in 3 waves with 35 idle
 // lanes (measured 6% faster at 20000 rows, 7% at 5000; with 4 words per
 // lane the same rule was slower).
-template <int K, int U, int V>
+template <int K, int U, int V, bool TAIL = false>
 static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
     const int64_t Wg = (R.W + V - 1) / V;
     int64_t cpw = kBlock / Wg;
@@ -326,8 +327,8 @@ static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipS
     }
     const int64_t threads = (cpw * Wg + kWave - 1) / kWave * kWave;
     const dim3 grid((unsigned)((R.P + cpw - 1) / cpw));
-    launch_index_t<K, U, V, true>(R, (uint32_t)cpw, grid, dim3((unsigned)threads), e, ties,
-                                  stream);
+    launch_index_t<K, U, V, true, TAIL>(R, (uint32_t)cpw, grid, dim3((unsigned)threads), e,
+                                        ties, stream);
 }
 
 // Tiling by matrix height.  Up to 1024 words (65536 rows) a workgroup holds
@@ -337,13 +338,20 @@ static void launch_aligned(const IndexRun &R, const EvalArgs &e, bool ties, hipS
 // faster than 2 words from 391 to 1016 words, equal at 344); as many
 // candidates per workgroup as fit, and a workgroup just large enough (whole
 // waves) to hold them.  Taller matrices use the flattened tiling with 2
-// words per lane.
+// words per lane.  With 2 words per lane up to 256 words, the last batch of
+// each series is cut to its remaining pairs (no loads past the series end:
+// 8.25 -> 7.53 us at 10000 rows, 9.33 -> 8.51 at 15000); above 256 words the
+// extra registers of that form cost resident waves and it is slower (10.8
+// -> 14.1 us at 20000 rows).
 constexpr int64_t kTwoWordsMax = 320;
+constexpr int64_t kTailMax = 256;
 
 template <int K, int U>
 static void launch_index_k(const IndexRun &R, const EvalArgs &e, bool ties, hipStream_t stream) {
     if (R.W <= kBlock / 2)
         launch_aligned<K, U, 1>(R, e, ties, stream);
+    else if (R.W <= kTailMax)
+        launch_aligned<K, U, 2, true>(R, e, ties, stream);
     else if (R.W <= kTwoWordsMax)
         launch_aligned<K, U, 2>(R, e, ties, stream);
     else if (R.W <= 4 * kBlock)
