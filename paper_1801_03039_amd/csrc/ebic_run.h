@@ -166,16 +166,6 @@ class Tabu {
     }
 
     size_t size() const { return used_; }
-    // Room for `entries` series of `cols` columns in all without growing:
-    // a run knows its bound (P per generation), and growing a large table
-    // step by step re-inserts every entry each time (random accesses to a
-    // table of tens of MB).
-    void reserve(size_t entries, size_t cols) {
-        size_t want = slots_.size();
-        while (want < 2 * entries) want *= 2;
-        if (want > slots_.size()) rehash(want);
-        arena_.reserve(cols);
-    }
     // The set as its series in insertion order (the arena and each entry's
     // length); loading re-inserts them.
     void save(Writer &w) const {
@@ -231,9 +221,8 @@ class Tabu {
                 return i;
         }
     }
-    void grow() { rehash(2 * slots_.size()); }
-    void rehash(size_t n) {
-        std::vector<Slot> old(n);
+    void grow() {
+        std::vector<Slot> old((size_t)2 * slots_.size());
         old.swap(slots_);
         const size_t mask = slots_.size() - 1;
         for (const Slot &e : old) {
@@ -579,7 +568,6 @@ class Run {
     Run(int32_t M, uint64_t seed, int32_t generations, const ebic_evolve_params &p)
         : p_(p), M_(M), generations_(generations), br_(p_, M, seed), toprank_(M) {
         tabu_limit_ = p.tabu_limit < 0 ? p.population : p.tabu_limit;
-        reserve_tabu();
         evalp_ = p.eval;
         evalp_.want_masks = 0;
     }
@@ -646,20 +634,11 @@ class Run {
         stopped_ = r.get<uint8_t>() != 0;
         if (!r.ok || gen_ < 0 || gens_run_ < 0 || first_ < 0) return false;
         if (!prev_.load(r, M_) || !tabu_.load(r) || !toprank_.load(r, M_)) return false;
-        reserve_tabu();
         cur_.clear();
         return gen_ == 0 || prev_.size() > 0;
     }
 
   private:
-    // The tabu list holds at most P series per generation (screened runs
-    // add only the kept children); reserved up to 2^21 series.
-    void reserve_tabu() {
-        const int64_t bound = std::min<int64_t>(
-            (int64_t)p_.population * ((int64_t)generations_ + 1), int64_t(1) << 21);
-        tabu_.reserve((size_t)bound, (size_t)bound * (size_t)(p_.len_min + p_.len_max) / 2);
-    }
-
     // Step 1: P distinct random series.
     void initial() {
         const int32_t P = p_.population;
