@@ -132,10 +132,11 @@ struct ebic_ctx {
     // per-call scratch
     unsigned long long *d_acc = nullptr;
     int64_t cap_P = 0;
-    // staging for the host-pointer entry point
-    int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr;
-    double *d_fit = nullptr;
+    // staging for the host-pointer entry point: offsets then columns, and
+    // fitness then counts, on the device and in pinned host memory
+    int32_t *d_cbf = nullptr, *h_cbf = nullptr;
+    double *d_res = nullptr, *h_res = nullptr;
     uint64_t *d_masks = nullptr;
-    int64_t cap_off = 0, cap_cols = 0, cap_out = 0, cap_masks = 0;
+    int64_t cap_cbf = 0, cap_res = 0, hcap_cbf = 0, hcap_res = 0, cap_masks = 0;
     std::string err;
 };

@@ -70,6 +70,24 @@ ebic_status grow(ebic_ctx *ctx, T *&ptr, int64_t &cap, int64_t need, bool zero) 
     return EBIC_OK;
 }
 
+// Pinned host staging (grown on demand; the caller has synchronised the
+// stream, so no copy is reading the old buffer).
+template <typename T>
+ebic_status grow_pinned(ebic_ctx *ctx, T *&ptr, int64_t &cap, int64_t need) {
+    if (need <= cap) return EBIC_OK;
+    const int64_t ncap = std::max<int64_t>(need, cap * 2);
+    if (ptr) {
+        HIP_TRY(ctx, hipHostFree(ptr));
+        ptr = nullptr;
+        cap = 0;
+    }
+    void *p = nullptr;
+    HIP_TRY(ctx, hipHostMalloc(&p, sizeof(T) * (size_t)ncap, hipHostMallocDefault));
+    ptr = static_cast<T *>(p);
+    cap = ncap;
+    return EBIC_OK;
+}
+
 ebic_status ensure_scratch(ebic_ctx *ctx, int64_t P) {
     return grow(ctx, ctx->d_acc, ctx->cap_P, P, true);
 }
@@ -304,10 +322,12 @@ ebic_status ebic_destroy(ebic_ctx *ctx) {
     if (!ctx) return EBIC_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_tie, ctx->d_acc, ctx->d_off,
-                    ctx->d_cols, ctx->d_counts, ctx->d_fit, ctx->d_masks};
+    void *bufs[] = {ctx->d_a, ctx->d_log, ctx->d_idx, ctx->d_tie, ctx->d_acc,
+                    ctx->d_cbf, ctx->d_res, ctx->d_masks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    if (ctx->h_cbf) (void)hipHostFree(ctx->h_cbf);
+    if (ctx->h_res) (void)hipHostFree(ctx->h_res);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return EBIC_OK;
@@ -384,15 +404,16 @@ ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *
     if (params->want_masks && !masks) return fail(ctx, EBIC_E_ARG, "want_masks needs masks");
     if (!check_cbf(ctx, offsets, cols, P, &st)) return st;
     const int64_t n_entries = offsets[P];
+    // One upload (offsets then columns) and one download (fitness then
+    // counts), both through pinned staging buffers.
+    const int64_t n_cbf = (int64_t)P + 1 + n_entries;      // int32
+    const int64_t n_res = (int64_t)P + ((int64_t)P + 1) / 2;  // doubles: P fitness + P int32
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if ((st = ensure_scratch(ctx, P)) != EBIC_OK) return st;
-    if ((st = grow(ctx, ctx->d_off, ctx->cap_off, (int64_t)P + 1, false)) != EBIC_OK) return st;
-    if ((st = grow(ctx, ctx->d_cols, ctx->cap_cols, std::max<int64_t>(n_entries, 1), false)) != EBIC_OK)
-        return st;
-    int64_t cap_c = ctx->cap_out, cap_f = ctx->cap_out;
-    if ((st = grow(ctx, ctx->d_counts, cap_c, P, false)) != EBIC_OK) return st;
-    if ((st = grow(ctx, ctx->d_fit, cap_f, P, false)) != EBIC_OK) return st;
-    ctx->cap_out = std::min(cap_c, cap_f);
+    if ((st = grow(ctx, ctx->d_cbf, ctx->cap_cbf, n_cbf, false)) != EBIC_OK) return st;
+    if ((st = grow(ctx, ctx->d_res, ctx->cap_res, n_res, false)) != EBIC_OK) return st;
+    if ((st = grow_pinned(ctx, ctx->h_cbf, ctx->hcap_cbf, n_cbf)) != EBIC_OK) return st;
+    if ((st = grow_pinned(ctx, ctx->h_res, ctx->hcap_res, n_res)) != EBIC_OK) return st;
     const int64_t mask_words = params->want_masks ? (int64_t)P * 2 * ctx->W : 0;
     if (mask_words && (st = grow(ctx, ctx->d_masks, ctx->cap_masks, mask_words, false)) != EBIC_OK)
         return st;
@@ -400,22 +421,25 @@ ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *
     if ((st = choose_path(ctx, params, &use_index)) != EBIC_OK) return st;
 
     hipStream_t s = ctx->stream;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_off, offsets, sizeof(int32_t) * ((size_t)P + 1),
+    std::memcpy(ctx->h_cbf, offsets, sizeof(int32_t) * ((size_t)P + 1));
+    std::memcpy(ctx->h_cbf + P + 1, cols, sizeof(int32_t) * (size_t)n_entries);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cbf, ctx->h_cbf, sizeof(int32_t) * (size_t)n_cbf,
                                 hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cols, cols, sizeof(int32_t) * (size_t)n_entries,
-                                hipMemcpyHostToDevice, s));
-    EvalArgs e{ctx->d_off, ctx->d_cols, P, n_entries, params->sigma, params->max_violations,
-               params->negative_trends ? 1 : 0, mask_words ? ctx->d_masks : nullptr,
-               ctx->d_counts, ctx->d_fit, ctx->d_log, ctx->d_acc};
+    int32_t *d_counts = reinterpret_cast<int32_t *>(ctx->d_res + P);
+    EvalArgs e{ctx->d_cbf, ctx->d_cbf + P + 1, P, n_entries, params->sigma,
+               params->max_violations, params->negative_trends ? 1 : 0,
+               mask_words ? ctx->d_masks : nullptr, d_counts, ctx->d_res, ctx->d_log,
+               ctx->d_acc};
     if ((st = launch_all(ctx, e, use_index, s)) != EBIC_OK) return st;
-    HIP_TRY(ctx, hipMemcpyAsync(counts, ctx->d_counts, sizeof(int32_t) * (size_t)P,
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(fitness, ctx->d_fit, sizeof(double) * (size_t)P,
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_res, ctx->d_res,
+                                sizeof(double) * (size_t)P + sizeof(int32_t) * (size_t)P,
                                 hipMemcpyDeviceToHost, s));
     if (mask_words)
         HIP_TRY(ctx, hipMemcpyAsync(masks, ctx->d_masks, sizeof(uint64_t) * (size_t)mask_words,
                                     hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    std::memcpy(fitness, ctx->h_res, sizeof(double) * (size_t)P);
+    std::memcpy(counts, ctx->h_res + P, sizeof(int32_t) * (size_t)P);
     return EBIC_OK;
 }
 
