@@ -264,12 +264,13 @@ ebic_status ebic_evolve_with(ebic_eval_fn eval, void *eval_user, int64_t n_rows,
  * Generations after warmup_generations draw a pool of oversample x (P -
  * elites) novel children and keep the P - elites that score ranks highest;
  * see ebic_evolve_surrogate for the pool rules.  score receives the pool as
- * host CBF (B series) and fills scores[B] (higher is better; NaN ranks last)
+ * host CBF (B series) and fills scores[B] (FP64, so exact fitness values rank
+ * as ebic_evolve_oversampled ranks them; higher is better; NaN ranks last)
  * and returns EBIC_OK.  host_threads (<= 0: the hardware's) draws the pool in
  * parallel; results do not depend on it.  eval as in ebic_evolve_with.
  */
 typedef ebic_status (*ebic_score_fn)(void *user, const int32_t *offsets, const int32_t *cols,
-                                     int32_t B, float *scores);
+                                     int32_t B, double *scores);
 ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_user, ebic_score_fn score,
                                       void *score_user, int64_t n_rows, int32_t n_cols,
                                       uint64_t seed, int32_t generations, int32_t oversample,

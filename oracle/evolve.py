@@ -223,6 +223,24 @@ def crossover(rng: SplitMix64, a: tuple, b: tuple, p: EvolveParams) -> tuple:
     return tuple(child)
 
 
+def tournament(rng, prev: Sequence[tuple], prev_fit: Sequence[float], penalty: Sequence[int],
+               size: int, base: float) -> int:
+    """Step 3 selection with the crowding penalty of Section 2.1: ``size``
+    draws i = uint(|prev|) with replacement; each draw's quality is its
+    fitness divided by base^theta, theta being the mean penalty of its
+    columns (their penalty sum over the series length); the first draw with
+    the strictly highest quality wins."""
+    best, best_adj = -1, float("-inf")
+    for _ in range(size):
+        i = rng.uint(len(prev))
+        si = prev[i]
+        vartheta = sum(penalty[c] for c in si) / len(si)
+        adj = prev_fit[i] / (base ** vartheta)
+        if adj > best_adj:
+            best, best_adj = i, adj
+    return best
+
+
 def evolve(a: np.ndarray, seed: int, generations: int, p: EvolveParams,
            on_generation: Optional[Callable[[Generation], None]] = None,
            keep_history: bool = True) -> Result:
@@ -281,21 +299,13 @@ def evolve(a: np.ndarray, seed: int, generations: int, p: EvolveParams,
             for c in s:
                 penalty[c] += 1
 
-        def tournament() -> int:
-            best, best_adj = -1, float("-inf")
-            for _ in range(p.tournament):
-                i = rng.uint(len(prev))
-                si = prev[i]
-                vartheta = sum(penalty[c] for c in si) / len(si)
-                adj = prev_fit[i] / (p.penalty_base ** vartheta)
-                if adj > best_adj:
-                    best, best_adj = i, adj
-            return best
+        def select() -> int:
+            return tournament(rng, prev, prev_fit, penalty, p.tournament, p.penalty_base)
 
         # Step 3: fill the population with novel children.
         hits = 0
         while len(new) < P:
-            ia = tournament()
+            ia = select()
             u = rng.uint(wsum)
             op, acc = 0, 0
             for op in range(5):
@@ -303,7 +313,7 @@ def evolve(a: np.ndarray, seed: int, generations: int, p: EvolveParams,
                 if u < acc:
                     break
             if op == OP_CROSSOVER:
-                ib = tournament()
+                ib = select()
                 child = crossover(rng, prev[ia], prev[ib], p)
             else:
                 child = tuple(mutate(rng, list(prev[ia]), op, p, n_cols))

@@ -465,7 +465,7 @@ def evolve_with(evaluate: Callable, n_rows: int, n_cols: int, seed: int, generat
 
 
 SCORE_FN = ctypes.CFUNCTYPE(_i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32,
-                            ctypes.POINTER(ctypes.c_float))
+                            ctypes.POINTER(ctypes.c_double))
 _evolve_screened_with = _sig("ebic_evolve_screened_with", _i32,
                              [EVAL_FN, _vp, SCORE_FN, _vp, _i64, _i32, _u64, _i32, _i32, _i32, _i32,
                               _P(EvolveParamsC), _P(_vp)])
@@ -478,7 +478,7 @@ def evolve_screened_with(evaluate: Callable, score: Callable, n_rows: int, n_col
                          on_generation: Optional[Callable[[Generation], None]] = None) -> EvolveResult:
     """Offspring-screened run with caller-supplied evaluator and ranking
     (``ebic_evolve_screened_with``).  ``evaluate`` as in ``evolve_with``;
-    ``score(offsets, cols)`` returns one float per pooled child (higher is
+    ``score(offsets, cols)`` returns one float64 per pooled child (higher is
     better)."""
     W = mask_words(n_rows)
     errors = []
@@ -505,7 +505,7 @@ def evolve_screened_with(evaluate: Callable, score: Callable, n_rows: int, n_col
             o = np.ctypeslib.as_array(off, shape=(B + 1,)).copy()
             n = int(o[-1])
             c = np.ctypeslib.as_array(cols, shape=(max(n, 1),))[:n].copy()
-            np.ctypeslib.as_array(out, shape=(B,))[:] = np.asarray(score(o, c), dtype=np.float32)
+            np.ctypeslib.as_array(out, shape=(B,))[:] = np.asarray(score(o, c), dtype=np.float64)
             return EBIC_OK
         except Exception as ex:
             errors.append(ex)

@@ -251,7 +251,7 @@ extern "C" ebic_status ebic_evolve_screened_with(ebic_eval_fn eval, void *eval_u
     *out = nullptr;
     Evaluator ev{eval, eval_user};
     auto scorer = [&](const Pop &pool, ebic_status *st) {
-        std::vector<float> sc((size_t)pool.size(), -INFINITY);
+        std::vector<double> sc((size_t)pool.size(), -INFINITY);
         ebic_status e = score(score_user, pool.off.data(), pool.cols.data(), pool.size(), sc.data());
         if (e != EBIC_OK) *st = e;
         return sc;

@@ -39,8 +39,8 @@ static ebic_status fake_eval(void *, const int32_t *off, const int32_t *cols, in
 }
 
 static ebic_status fake_score(void *, const int32_t *off, const int32_t *cols, int32_t B,
-                              float *s) {
-    for (int32_t i = 0; i < B; ++i) s[i] = (float)((off[i + 1] - off[i]) * 7 % 13) + cols[off[i]] * 1e-3f;
+                              double *s) {
+    for (int32_t i = 0; i < B; ++i) s[i] = (double)((off[i + 1] - off[i]) * 7 % 13) + cols[off[i]] * 1e-3;
     return EBIC_OK;
 }
 

@@ -49,9 +49,13 @@ def test_create_argument_errors_before_device_work():
     assert b._create(ptr, 0, 3, 3, 0, 0, ctypes.byref(h)) == b.EBIC_E_ARG
     assert b._create(ptr, 4, 0, 3, 0, 0, ctypes.byref(h)) == b.EBIC_E_ARG
     assert b._create(ptr, 4, 3, 2, 0, 0, ctypes.byref(h)) == b.EBIC_E_ARG   # ld < n_cols
+    assert b"leading dimension" in b._last_error(None)
+    assert b._create(ptr, 4, 3, 3, 1, 0, ctypes.byref(h)) == b.EBIC_E_ARG   # col-major, ld < n_rows
+    assert b"leading dimension" in b._last_error(None)
     assert b._create(ptr, 4, 3, 3, 7, 0, ctypes.byref(h)) == b.EBIC_E_ARG   # layout
+    assert b"layout" in b._last_error(None)
     assert b._create(ptr, 4, 3, 3, 0, 0, None) == b.EBIC_E_ARG
-    assert b"leading dimension" in b._last_error(None) or True
+    assert b"out is null" in b._last_error(None)
     assert b._evaluate(None, None, None, 1, None, None, None, None) == b.EBIC_E_ARG
     prm = e.make_params(1)
     assert b._evaluate_device(None, None, None, 1, 0, ctypes.byref(prm), None, None, None,

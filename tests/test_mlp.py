@@ -63,10 +63,15 @@ def test_forward_and_gradients_match_oracle(E, M, D, H, B):
         loss, g = net.gradients(off, cols, t)
         l_ref, g_ref, _ = omlp.loss_and_grad(p, off, cols, t, M, D, H, bf16=True)
         assert abs(loss - l_ref) <= 1e-2 * max(1.0, l_ref)
+        # element by element within 1e-2 of the block's largest reference
+        # gradient (FP32 accumulation in a different order than the float64
+        # oracle, same BF16 rounding points)
         for name, sl in _blocks(M, D, H).items():
             ref = g_ref[sl]
-            err = np.linalg.norm(g[sl] - ref) / max(np.linalg.norm(ref), 1e-12)
-            assert err < 2e-2, (name, err)
+            bound = 1e-2 * max(float(np.max(np.abs(ref))), 1e-30)
+            err = float(np.max(np.abs(g[sl] - ref)))
+            _note(f"  {name}: max |g - g_ref| = {err:.3e}, bound {bound:.3e}")
+            assert err <= bound, (name, err, bound)
 
 
 def test_adam_step_matches_oracle(E):
