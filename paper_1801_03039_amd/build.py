@@ -25,7 +25,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 SOURCES = ["ebic_kernels.hip", "ebic_batch_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
            "ebic_mlp_kernels.hip", "ebic_mlp.cpp", "ebic_surrogate.cpp", "ebic_scores.hip",
-           "ebic_checkpoint.cpp"]
+           "ebic_checkpoint.cpp", "ebic_noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
           "-I", INCLUDE, "-I", CSRC]
@@ -40,19 +40,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source and link the library.  With ``incremental``, an
+    object newer than its source and every header is reused."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     cc = hipcc()
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    newest_header = max(os.path.getmtime(h) for h in headers)
     cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD_DIR, src + ".o")
+        objs.append(obj)
+        if (incremental and os.path.exists(obj) and
+                os.path.getmtime(obj) > max(os.path.getmtime(path), newest_header)):
+            continue
         cmds.append([cc, "-c"] + (HIP_ONLY if src.endswith(".hip") else []) + [path, "-o", obj] +
                     COMMON)
-        objs.append(obj)
     # sources compile in parallel (a few hipcc processes; the kernel files
     # dominate the build time)
-    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "4")), os.cpu_count() or 1))
+    jobs = max(1, min(len(cmds) or 1, int(os.environ.get("MAX_JOBS", "4")), os.cpu_count() or 1))
     with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
         procs = []
         for cmd in cmds:
@@ -71,4 +79,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))
