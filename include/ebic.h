@@ -163,6 +163,34 @@ ebic_status ebic_evaluate_device(ebic_ctx *ctx, const int32_t *d_offsets, const 
                                  uint64_t *d_masks, int32_t *d_counts, double *d_fitness,
                                  void *hip_stream);
 
+/*
+ * ebic_evaluate_device_noalloc: for callers that cannot allocate device
+ * memory -- code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results, stream ordering and
+ * validation as ebic_evaluate_device; the call itself allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).
+ *   Scratch: the per-candidate accumulators of the evaluation live in a
+ *   fixed device array of EBIC_NOALLOC_MAX_CANDIDATES 8-byte entries
+ *   (512 KiB) that the library holds on every device it runs on until the
+ *   process ends (its address is taken when the first context on the device
+ *   is created).  Each call clears the P entries it uses, with a fill kernel
+ *   on hip_stream, before evaluating.  All calls on one GPU share that array:
+ *   calls that overlap in time on one GPU (other streams, other contexts,
+ *   other threads) race and must be serialised by the caller.
+ *   Path: the order index is used only if it is already built (after
+ *   ebic_set_path(ctx, EBIC_PATH_INDEX), or after an evaluation that built
+ *   it); otherwise the direct kernel runs (identical results).
+ * Errors: as ebic_evaluate_device; E_RANGE for P >
+ * EBIC_NOALLOC_MAX_CANDIDATES; E_DEVICE if the array's address could not be
+ * obtained on the context's device.
+ */
+#define EBIC_NOALLOC_MAX_CANDIDATES 65536
+ebic_status ebic_evaluate_device_noalloc(ebic_ctx *ctx, const int32_t *d_offsets,
+                                         const int32_t *d_cols, int32_t P, int64_t n_entries,
+                                         const ebic_params *params, uint64_t *d_masks,
+                                         int32_t *d_counts, double *d_fitness,
+                                         void *hip_stream);
+
 /* Wait for all work on the context's stream. */
 ebic_status ebic_synchronize(ebic_ctx *ctx);
 

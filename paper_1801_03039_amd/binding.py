@@ -100,12 +100,16 @@ _get_info = _sig("ebic_get_info", _i32, [_vp, _P(CtxInfo)])
 _evaluate = _sig("ebic_evaluate", _i32, [_vp, _vp, _vp, _i32, _P(Params), _vp, _vp, _vp])
 _evaluate_device = _sig("ebic_evaluate_device", _i32,
                         [_vp, _vp, _vp, _i32, _i64, _P(Params), _vp, _vp, _vp, _vp])
+_evaluate_device_noalloc = _sig("ebic_evaluate_device_noalloc", _i32,
+                                [_vp, _vp, _vp, _i32, _i64, _P(Params), _vp, _vp, _vp, _vp])
+NOALLOC_MAX_CANDIDATES = 65536
 _synchronize = _sig("ebic_synchronize", _i32, [_vp])
 _last_error = _sig("ebic_last_error", ctypes.c_char_p, [_vp])
 
 EXPORTED = ["ebic_create", "ebic_create_device", "ebic_destroy", "ebic_mask_words",
             "ebic_set_path", "ebic_set_index_budget", "ebic_get_info", "ebic_evaluate",
-            "ebic_evaluate_device", "ebic_synchronize", "ebic_last_error"]
+            "ebic_evaluate_device", "ebic_evaluate_device_noalloc", "ebic_synchronize",
+            "ebic_last_error"]
 
 
 class EbicError(RuntimeError):
@@ -216,20 +220,23 @@ class Context:
     # -- device tensors ---------------------------------------------------------
     def evaluate_device(self, offsets, cols, counts, fitness, masks=None, *, sigma: int,
                         max_violations: int = 0, negative_trends: bool = False,
-                        stream=None) -> None:
+                        stream=None, noalloc: bool = False) -> None:
         """Stream-ordered evaluation of device tensors (int32 offsets/cols,
         int32 counts, float64 fitness, optional uint64/int64 masks [P,2,W]).
         Launches on ``stream`` (default: torch's current stream) and returns
-        without waiting."""
+        without waiting.  ``noalloc`` calls ``ebic_evaluate_device_noalloc``
+        (no device allocation; P <= NOALLOC_MAX_CANDIDATES)."""
         self.device_call(offsets, cols, counts, fitness, masks, sigma=sigma,
                          max_violations=max_violations, negative_trends=negative_trends,
-                         stream=stream)()
+                         stream=stream, noalloc=noalloc)()
 
     def device_call(self, offsets, cols, counts, fitness, masks=None, *, sigma: int,
-                    max_violations: int = 0, negative_trends: bool = False, stream=None):
+                    max_violations: int = 0, negative_trends: bool = False, stream=None,
+                    noalloc: bool = False):
         """Validate the tensors once and return a no-argument callable that
-        launches ``ebic_evaluate_device`` on them (the tensors must stay
-        alive and keep their storage while the callable is used)."""
+        launches ``ebic_evaluate_device`` (``ebic_evaluate_device_noalloc``
+        with ``noalloc``) on them (the tensors must stay alive and keep their
+        storage while the callable is used)."""
         import torch
         P = offsets.numel() - 1
         for t, name in ((offsets, "offsets"), (cols, "cols"), (counts, "counts"),
@@ -253,7 +260,7 @@ class Context:
         args = (h, _vp(offsets.data_ptr()), _vp(cols.data_ptr()), P, cols.numel(),
                 ctypes.byref(prm), _vp(masks.data_ptr()) if want else None,
                 _vp(counts.data_ptr()), _vp(fitness.data_ptr()), _vp(stream.cuda_stream))
-        fn = _evaluate_device
+        fn = _evaluate_device_noalloc if noalloc else _evaluate_device
 
         def call():
             st = fn(*args)

@@ -91,6 +91,20 @@ hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream);
 // Workgroups of the batch kernel resident per compute unit.
 int batch_wgs_per_cu();
 
+// Device-pointer evaluation (ebic_runtime.cpp).  acc == nullptr: the
+// context's own accumulators, grown on demand, and the order index built on
+// first need.  Otherwise acc holds >= P zeroed accumulators and nothing is
+// allocated; the index is used only if it is already built.
+ebic_status evaluate_device_impl(ebic_ctx *ctx, const int32_t *d_offsets, const int32_t *d_cols,
+                                 int32_t P, int64_t n_entries, const ebic_params *params,
+                                 uint64_t *d_masks, int32_t *d_counts, double *d_fitness,
+                                 void *hip_stream, unsigned long long *acc);
+// Records msg as the context's (or, for ctx == nullptr, the thread's) error.
+ebic_status fail_status(ebic_ctx *ctx, ebic_status st, const char *msg);
+// Looks up the current device's no-allocation scratch array once
+// (ebic_noalloc.hip); called with `device` current.
+hipError_t noalloc_setup(int device);
+
 // Runtime helpers shared with the multi-run driver (ebic_runtime.cpp).
 void set_thread_error(const char *msg);
 ebic_status ensure_index(ebic_ctx *ctx);  // builds the order index if missing

@@ -209,6 +209,9 @@ ebic_status create_common(const float *a, bool on_device, int64_t n_rows, int32_
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipSetDevice"));
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipStreamCreate"));
+    // Once per device: the address of its no-allocation scratch array.  A
+    // failure is kept and reported by the entry point that needs it.
+    (void)noalloc_setup(device);
 
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
@@ -292,6 +295,46 @@ bool check_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32
 }  // namespace
 
 namespace ebic {
+// Shared body of the device-pointer entry points.  acc == nullptr: the
+// context's accumulators (grown on demand) and the index built on first
+// need.  Otherwise `acc` holds >= P zeroed accumulators and nothing is
+// allocated: the index is used only if it is already built.
+ebic_status evaluate_device_impl(ebic_ctx *ctx, const int32_t *d_offsets, const int32_t *d_cols,
+                                 int32_t P, int64_t n_entries, const ebic_params *params,
+                                 uint64_t *d_masks, int32_t *d_counts, double *d_fitness,
+                                 void *hip_stream, unsigned long long *acc) {
+    if (!ctx) return fail(nullptr, EBIC_E_ARG, "ctx is null");
+    ebic_status st;
+    if (!params_ok(ctx, params, &st)) return st;
+    if (P < 0 || n_entries < 0) return fail(ctx, EBIC_E_ARG, "P and n_entries must be >= 0");
+    if (P == 0) return EBIC_OK;
+    if (!d_offsets || !d_counts || !d_fitness || (n_entries > 0 && !d_cols))
+        return fail(ctx, EBIC_E_ARG, "null device pointer");
+    if (params->want_masks && !d_masks) return fail(ctx, EBIC_E_ARG, "want_masks needs masks");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    bool use_index = false;
+    if (!acc) {
+        st = ensure_scratch(ctx, P);
+        if (st != EBIC_OK) return st;
+        acc = ctx->d_acc;
+        st = choose_path(ctx, params, &use_index);
+        if (st != EBIC_OK) return st;
+    } else {
+        use_index = ctx->idx_built && ctx->path != EBIC_PATH_DIRECT &&
+                    params->max_violations <= kIndexMaxViolations &&
+                    !(ctx->path == EBIC_PATH_AUTO && ctx->idx_bytes > ctx->idx_budget);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    EvalArgs e{d_offsets, d_cols, P, n_entries, params->sigma, params->max_violations,
+               params->negative_trends ? 1 : 0, params->want_masks ? d_masks : nullptr,
+               d_counts, d_fitness, ctx->d_log, acc};
+    return launch_all(ctx, e, use_index, s);
+}
+
+ebic_status fail_status(ebic_ctx *ctx, ebic_status st, const char *msg) {
+    return fail(ctx, st, msg);
+}
+
 void set_thread_error(const char *msg) { g_tls_error = msg; }
 ebic_status ensure_index(ebic_ctx *ctx) { return build_index(ctx); }
 bool valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
@@ -370,25 +413,8 @@ ebic_status ebic_evaluate_device(ebic_ctx *ctx, const int32_t *d_offsets, const 
                                  int32_t P, int64_t n_entries, const ebic_params *params,
                                  uint64_t *d_masks, int32_t *d_counts, double *d_fitness,
                                  void *hip_stream) {
-    if (!ctx) return fail(nullptr, EBIC_E_ARG, "ctx is null");
-    ebic_status st;
-    if (!params_ok(ctx, params, &st)) return st;
-    if (P < 0 || n_entries < 0) return fail(ctx, EBIC_E_ARG, "P and n_entries must be >= 0");
-    if (P == 0) return EBIC_OK;
-    if (!d_offsets || !d_counts || !d_fitness || (n_entries > 0 && !d_cols))
-        return fail(ctx, EBIC_E_ARG, "null device pointer");
-    if (params->want_masks && !d_masks) return fail(ctx, EBIC_E_ARG, "want_masks needs masks");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    st = ensure_scratch(ctx, P);
-    if (st != EBIC_OK) return st;
-    bool use_index = false;
-    st = choose_path(ctx, params, &use_index);
-    if (st != EBIC_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    EvalArgs e{d_offsets, d_cols, P, n_entries, params->sigma, params->max_violations,
-               params->negative_trends ? 1 : 0, params->want_masks ? d_masks : nullptr,
-               d_counts, d_fitness, ctx->d_log, ctx->d_acc};
-    return launch_all(ctx, e, use_index, s);
+    return ebic::evaluate_device_impl(ctx, d_offsets, d_cols, P, n_entries, params, d_masks,
+                                      d_counts, d_fitness, hip_stream, nullptr);
 }
 
 ebic_status ebic_evaluate(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, int32_t P,
