@@ -137,22 +137,52 @@ def _np_ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(_vp)
 
 
+def _strided_layout(shape, strides):
+    """(layout, ld) of a 2-D float32 view with element strides, if the
+    library can read it in place: rows or columns contiguous with a leading
+    dimension at least the row or column length; else None."""
+    n, m = shape
+    s0, s1 = strides
+    if s1 == 1 and (s0 >= m or n == 1):
+        return EBIC_ROW_MAJOR, max(s0, m) if n > 1 else m
+    if s0 == 1 and (s1 >= n or m == 1):
+        return EBIC_COL_MAJOR, max(s1, n) if m > 1 else n
+    return None
+
+
 class Context:
-    """A matrix resident on one GPU (``ebic_create``)."""
+    """A matrix resident on one GPU (``ebic_create``).  A float32 matrix view
+    whose rows (or columns) are contiguous is read in place, with its leading
+    dimension (EBIC_ROW_MAJOR / EBIC_COL_MAJOR); other views are copied."""
 
     def __init__(self, a, device: int = 0, path: str = "auto"):
         h = _vp()
         if hasattr(a, "is_cuda") and a.is_cuda:
-            t = a.contiguous()
+            t = a
             if t.dtype.itemsize != 4 or not t.dtype.is_floating_point:
                 raise TypeError("matrix must be float32")
+            if t.dim() != 2:
+                raise ValueError("matrix must be 2-D")
             n, m = t.shape
-            _check(_create_device(_vp(t.data_ptr()), n, m, m, EBIC_ROW_MAJOR,
+            lay = _strided_layout((n, m), t.stride())
+            if lay is None:
+                t = t.contiguous()
+                lay = (EBIC_ROW_MAJOR, m)
+            _check(_create_device(_vp(t.data_ptr()), n, m, lay[1], lay[0],
                                   int(t.device.index or 0), ctypes.byref(h)))
         else:
-            arr = np.ascontiguousarray(a, dtype=np.float32)
+            arr = np.asarray(a)
+            if arr.dtype != np.float32 or arr.ndim != 2:
+                arr = np.asarray(arr, dtype=np.float32)
+            if arr.ndim != 2:
+                raise ValueError("matrix must be 2-D")
             n, m = arr.shape
-            _check(_create(_np_ptr(arr), n, m, m, EBIC_ROW_MAJOR, int(device), ctypes.byref(h)))
+            lay = _strided_layout((n, m), tuple(x // 4 for x in arr.strides))
+            if lay is None or any(x % 4 for x in arr.strides):
+                arr = np.ascontiguousarray(arr)
+                lay = (EBIC_ROW_MAJOR, m)
+            _check(_create(_vp(arr.ctypes.data), n, m, lay[1], lay[0], int(device),
+                           ctypes.byref(h)))
         self._h = h
         self.n_rows, self.n_cols = int(n), int(m)
         self.W = mask_words(self.n_rows)

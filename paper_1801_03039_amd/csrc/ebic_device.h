@@ -101,7 +101,8 @@ __device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, i
 // pairwise order index and folds the violation words (complements) into K+1
 // saturating bit-sliced counters per direction: c[i] has bit b set when row
 // b has more than i violations.  lt(q,p) is read only for pairs whose tie
-// flag is set; otherwise it is ~lt(p,q).  Loads for kUnroll pairs are issued before
+// flag is set; otherwise it is ~lt(p,q) (lt(p,p) itself for a repeated
+// column).  Loads for kUnroll pairs are issued before
 // any is consumed (the lane's latency chain is one order-word round trip per
 // kUnroll pairs), and a lane stops once every row of its word is rejected in
 // every enabled direction.
@@ -334,8 +335,10 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                         if (TIES && tf[u]) {
                             load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
                         } else {
+                            // a repeated column is its own reverse: lt(p,p) = 0
+                            const bool self = !TIES && q[u] == pp;
 #pragma unroll
-                            for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
+                            for (int v = 0; v < V; ++v) ld[u][v] = self ? lu[u][v] : ~lu[u][v];
                         }
                         pp = q[u];
                     }
@@ -400,8 +403,10 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                         if (TIES && tf[u]) {
                             load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
                         } else {
+                            // a repeated column is its own reverse: lt(p,p) = 0
+                            const bool self = !TIES && q[u] == pp;
 #pragma unroll
-                            for (int v = 0; v < V; ++v) ld[u][v] = ~lu[u][v];
+                            for (int v = 0; v < V; ++v) ld[u][v] = self ? lu[u][v] : ~lu[u][v];
                         }
 #pragma unroll
                         for (int v = 0; v < V; ++v) ld[u][v] = t + u < L ? ld[u][v] : ~0ull;

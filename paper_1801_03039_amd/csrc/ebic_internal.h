@@ -29,9 +29,11 @@ struct DeviceBuf {
 hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int32_t layout,
                          int64_t npad, float *dst, hipStream_t stream);
 
-// Builds the pairwise order index and its per-pair tie flags (m*m bytes).
+// Builds the pairwise order index, its per-pair tie flags (m*m bytes) and
+// any_tie[0] = whether two distinct columns tie on some row.
 hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
-                              int64_t wpad, uint64_t *idx, uint8_t *tie, hipStream_t stream);
+                              int64_t wpad, uint64_t *idx, uint8_t *tie, int32_t *any_tie,
+                              hipStream_t stream);
 
 struct EvalArgs {
     const int32_t *offsets;
@@ -136,8 +138,8 @@ struct ebic_ctx {
     double *d_log = nullptr;     // ln(i), i = 0..n
     // pairwise order index
     uint64_t *d_idx = nullptr;
-    uint8_t *d_tie = nullptr;    // m*m tie flags of the index
-    bool any_tie = true;         // some tie flag is set (known once the index is built)
+    uint8_t *d_tie = nullptr;    // m*m tie flags of the index, then an int32 any-tie flag
+    bool any_tie = true;         // two distinct columns tie (known once the index is built)
     int64_t idx_bytes = 0;
     int64_t idx_budget = 0;
     bool idx_built = false;

@@ -10,7 +10,7 @@
 // Layouts
 //   matrix  column-major FP32 a[j*npad + r], npad = 64*ceil(n/64), pad rows 0
 //   index   idx[(p*m + q)*wpad + w]: bit b set when row 64w+b < n has
-//           a[r,p] < a[r,q]; wpad = W rounded up to 8 words (64 bytes)
+//           a[r,p] < a[r,q]; wpad = W rounded up to 16 words (128 bytes)
 //   masks   masks[(c*2 + dir)*W + w], dir 0 rising, dir 1 falling
 //
 // One evaluation is one kernel launch: the part of each candidate that
@@ -59,63 +59,161 @@ __global__ __launch_bounds__(kBlock) void ingest_cols_kernel(const float *__rest
 
 // ----------------------------------------------------------- index build --
 //
-// One wave per (64-row word w, block of kPB columns p).  Lane = row.  The
-// kPB values a[r,p] stay in registers while the wave streams every column q
-// once: each compare is one ballot giving 64 rows of lt(p,q) at once.
-constexpr int kPB = 16;
+// Workgroup = 4 waves over one block of kRW consecutive 64-row words (lane =
+// row within each word), one group of kPG columns p (kPW per wave, their
+// values for the block's rows held in registers) and one chunk of kQC
+// columns q.  Each unordered pair {p, q} is built by one wave: the wave
+// whose p columns hold the smaller column (q < p0 is skipped; in a diagonal
+// block some words are written twice, with equal values).  Per q and word
+// the wave takes two ballots, lt = (a[r,p] < a[r,q]) and gt = (a[r,q] <
+// a[r,p]); lt is word w of order row (p,q), and a valid row in neither
+// (equal values, or a NaN) ties the pair.  Only lt is moved into the lane
+// that stores it (lane kRW*i + j holds column p0+i and word j, two
+// v_writelane); order row (q,p) is then ~lt restricted to the valid rows,
+// minus the tied rows, which are moved into the lanes only for the rare
+// (pair, q) that has one.  One store instruction writes kRW contiguous
+// words (128 bytes) of each of kPW order rows, and one more the kPW
+// reverse rows.
+//
+// Tie flags: tie[p*m + q] = tie[q*m + p] = 1 for a tied pair (zeroed before
+// the launch; every writer stores 1), and any_tie[0] = 1 when a pair of
+// distinct columns ties (a column always ties with itself: lt(p,p) = 0).
+//
+// A ballot of an ordered not-equal compare is avoided: the compiler lowers
+// it to the unordered form (true for NaN); lt and gt are ordered less-than
+// compares.
+constexpr int kRW = 16;               // 64-row words per row block
+constexpr int kPW = 4;                // columns p per wave
+constexpr int kPG = kPW * kBlock / kWave;   // columns p per workgroup (16)
+constexpr int kQC = 16;               // columns q per workgroup
+static_assert(kPW * kRW == kWave, "one stored word per lane");
+static_assert(kQC == kPG, "a column group and a column chunk cover the same columns");
 
-__global__ __launch_bounds__(kBlock) void index_build_kernel(const float *__restrict__ a,
-                                                             int64_t n, int64_t npad, int32_t m,
-                                                             int64_t W, int64_t wpad,
-                                                             int64_t wblocks,
-                                                             uint64_t *__restrict__ idx) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int64_t wb = blockIdx.x % wblocks;
-    const int32_t p0 = (int32_t)(blockIdx.x / wblocks) * kPB;
-    const int64_t w = wb * 4 + wv;
-    if (w >= W) return;  // uniform per wave
-    const int64_t r = w * 64 + lane;
-    const bool valid = r < n;
-    float vp[kPB];
-#pragma unroll
-    for (int i = 0; i < kPB; ++i) vp[i] = (p0 + i < m) ? a[(int64_t)(p0 + i) * npad + r] : 0.0f;
-    const bool writer = lane < kPB && p0 + lane < m;
-    uint64_t *out = idx + ((int64_t)(p0 + lane) * m) * wpad + w;
-    for (int32_t q = 0; q < m; ++q) {
-        const float vq = a[(int64_t)q * npad + r];
-        uint64_t mine = 0;
-#pragma unroll
-        for (int i = 0; i < kPB; ++i) {
-            const uint64_t bits = ballot(valid && vp[i] < vq);
-            mine = (lane == i) ? bits : mine;
-        }
-        if (writer) out[(int64_t)q * wpad] = mine;
-    }
+// v_writelane_b32 through its LLVM intrinsic (clang has no builtin for it):
+// lane `lane` of the result takes the uniform value `src`, the other lanes
+// keep `old`.  It moves a ballot (two SGPRs) into the lane that stores it.
+__device__ int32_t amdgcn_writelane(int32_t src, int32_t lane, int32_t old)
+    __asm("llvm.amdgcn.writelane.i32");
+
+__global__ __launch_bounds__(kBlock) void index_fill_kernel(uint8_t *__restrict__ tie,
+                                                            int64_t n_bytes,
+                                                            int32_t *__restrict__ any_tie) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n_bytes) tie[i] = 0;
+    if (i == 0) any_tie[0] = 0;
 }
 
-// Tie flags: tie[p*m + q] = 1 when some row r < n has a[r,p] and a[r,q]
-// equal or unordered (NaN), i.e. when neither lt(p,q) nor lt(q,p) holds.
-// For a pair without such a row the falling test needs no second order
-// word: lt(q,p) = ~lt(p,q) on every row.  One wave per ordered pair, lanes
-// over words.
-__global__ __launch_bounds__(kBlock) void tie_flags_kernel(const uint64_t *__restrict__ idx,
-                                                           int64_t n, int32_t m, int64_t W,
-                                                           int64_t wpad,
-                                                           uint8_t *__restrict__ tie) {
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t pair = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
-         pair < (int64_t)m * m; pair += waves) {  // uniform per wave
-        const int64_t p = pair / m, q = pair - p * m;
-        const uint64_t *pq = idx + pair * wpad;
-        const uint64_t *qp = idx + (q * m + p) * wpad;
-        bool any = false;
-        for (int64_t w = lane; w < W; w += kWave)
-            any |= (~(pq[w] | qp[w]) & tail_bits(n, w, W)) != 0ull;
-        const uint64_t hit = ballot(any);
-        if (lane == 0) tie[pair] = hit ? 1 : 0;
+__global__ __launch_bounds__(kBlock) void index_build_kernel(
+    const float *__restrict__ a, int64_t n, int64_t npad, int32_t m, int64_t W, int64_t wpad,
+    int32_t G, int64_t pairs, int64_t tiles, int64_t per_xcd, uint64_t *__restrict__ idx,
+    uint8_t *__restrict__ tie, int32_t *__restrict__ any_tie) {
+    // Tiles in (row block, column-group pair) order; XCD x (workgroups are
+    // dealt round-robin to the 8 XCDs) takes the x-th contiguous range, so
+    // the workgroups of a row block share one L2.
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (t >= tiles) return;
+    const int64_t rb = t / pairs;
+    int64_t k = t - rb * pairs;
+    // k-th pair (g, h), g <= h < G, in row-major order of the upper triangle
+    int32_t g = 0;
+    {
+        int32_t lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            const int64_t first = (int64_t)mid * G - (int64_t)mid * (mid - 1) / 2;
+            if (first <= k) lo = mid; else hi = mid - 1;
+        }
+        g = lo;
+        k -= (int64_t)g * G - (int64_t)g * (g - 1) / 2;
     }
+    const int32_t h = g + (int32_t)k;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t p0 = g * kPG + wv * kPW;
+    if (p0 >= m) return;                                    // uniform per wave
+    const int32_t q_lo = max(h * kQC, p0), q_hi = min(h * kQC + kQC, m);
+    if (q_lo >= q_hi) return;                               // uniform per wave
+    const int64_t w0 = rb * kRW;
+    const int32_t jn = (int32_t)min<int64_t>(kRW, W - w0);   // words of the block in the matrix
+    const uint64_t last = tail_bits(n, w0 + jn - 1, W);      // rows of its last word
+    // Word j of the block: rows r = 64*(w0 + j) + lane.  Loads past the
+    // matrix (j >= jn, or a column past m) read a clamped, valid address and
+    // their results are masked off.
+    auto row_of = [&](int j) { return min<int64_t>(w0 + j, W - 1) * 64 + lane; };
+
+    float vp[kPW][kRW];
+#pragma unroll
+    for (int i = 0; i < kPW; ++i) {
+        const float *col = a + (int64_t)min(p0 + i, m - 1) * npad;
+#pragma unroll
+        for (int j = 0; j < kRW; ++j) vp[i][j] = col[row_of(j)];
+    }
+    // the (column, word) this lane stores, and the valid rows of that word
+    const int32_t sp = p0 + lane / kRW;
+    const int64_t sw = w0 + lane % kRW;
+    const bool store = sp < m && sw < W;
+    const uint64_t sw_valid = sw < W ? tail_bits(n, sw, W) : 0ull;
+
+    // FULL: every row of the block's kRW words is in the matrix (all but
+    // the last block), so no valid-row masks are needed.
+    auto run = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        auto valid = [&](int j) -> uint64_t {
+            if constexpr (FULL) return ~0ull;
+            else return j + 1 < jn ? ~0ull : (j + 1 == jn ? last : 0ull);
+        };
+        for (int32_t q = q_lo; q < q_hi; ++q) {
+            float vq[kRW];
+            const float *col = a + (int64_t)q * npad;
+#pragma unroll
+            for (int j = 0; j < kRW; ++j) vq[j] = col[row_of(j)];
+            int32_t lt_lo = 0, lt_hi = 0, tie_lo = 0, tie_hi = 0;
+            uint64_t tied = 0;   // some valid row of the block ties the pair (p0+i, q)
+#pragma unroll
+            for (int i = 0; i < kPW; ++i) {
+                uint64_t ti = 0;
+#pragma unroll
+                for (int j = 0; j < kRW; ++j) {
+                    // pad rows hold 0 in every column, so lt is 0 there
+                    const uint64_t lt = ballot(vp[i][j] < vq[j]);
+                    const uint64_t gt = ballot(vq[j] < vp[i][j]);
+                    ti |= valid(j) & ~(lt | gt);
+                    lt_lo = amdgcn_writelane((int32_t)(uint32_t)lt, i * kRW + j, lt_lo);
+                    lt_hi = amdgcn_writelane((int32_t)(uint32_t)(lt >> 32), i * kRW + j, lt_hi);
+                }
+                tied |= (ti != 0ull ? 1ull : 0ull) << i;
+            }
+            if (tied != 0ull) {   // rare (always for q in [p0, p0 + kPW))
+                // the tied rows of each tied pair, word by word: equal values or a NaN
+#pragma unroll
+                for (int i = 0; i < kPW; ++i) {
+                    if (!((tied >> i) & 1ull) || p0 + i >= m) continue;
+#pragma unroll
+                    for (int j = 0; j < kRW; ++j) {
+                        const uint64_t t = (ballot(vp[i][j] == vq[j]) | ballot(vp[i][j] != vp[i][j]) |
+                                            ballot(vq[j] != vq[j])) & valid(j);
+                        tie_lo = amdgcn_writelane((int32_t)(uint32_t)t, i * kRW + j, tie_lo);
+                        tie_hi = amdgcn_writelane((int32_t)(uint32_t)(t >> 32), i * kRW + j,
+                                                  tie_hi);
+                    }
+                    if (lane == 0) {
+                        tie[(int64_t)(p0 + i) * m + q] = 1;
+                        tie[(int64_t)q * m + p0 + i] = 1;
+                        if (p0 + i != q) any_tie[0] = 1;
+                    }
+                }
+            }
+            if (store) {
+                const uint64_t lt = ((uint64_t)(uint32_t)lt_hi << 32) | (uint32_t)lt_lo;
+                const uint64_t tw = ((uint64_t)(uint32_t)tie_hi << 32) | (uint32_t)tie_lo;
+                idx[((int64_t)sp * m + q) * wpad + sw] = lt;
+                idx[((int64_t)q * m + sp) * wpad + sw] = ~lt & sw_valid & ~tw;
+            }
+        }
+    };
+    if (jn == kRW && last == ~0ull)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 }
 
 // ------------------------------------------------------- direct evaluator --
@@ -242,19 +340,22 @@ hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int
 }
 
 hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
-                              int64_t wpad, uint64_t *idx, uint8_t *tie, hipStream_t stream) {
-    const int64_t wblocks = (W + 3) / 4;
-    const int64_t pblocks = (m + kPB - 1) / kPB;
-    hipLaunchKernelGGL(index_build_kernel, dim3((unsigned)(wblocks * pblocks)), dim3(kBlock), 0,
-                       stream, a, n, npad, m, W, wpad, wblocks, idx);
+                              int64_t wpad, uint64_t *idx, uint8_t *tie, int32_t *any_tie,
+                              hipStream_t stream) {
+    const int64_t flags = (int64_t)m * m;
+    hipLaunchKernelGGL(index_fill_kernel, dim3((unsigned)((flags + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, stream, tie, flags, any_tie);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t pairs = (int64_t)m * m;
-    const int64_t waves_per_block = kBlock / kWave;
-    int64_t blocks = (pairs + waves_per_block - 1) / waves_per_block;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(tie_flags_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, idx, n, m,
-                       W, wpad, tie);
+    const int32_t G = (m + kPG - 1) / kPG;
+    const int64_t pairs = (int64_t)G * (G + 1) / 2;
+    const int64_t rblocks = (W + kRW - 1) / kRW;
+    const int64_t tiles = rblocks * pairs;
+    const int64_t per_xcd = (tiles + kXcds - 1) / kXcds;
+    const int64_t grid = per_xcd * kXcds;
+    if (grid > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(index_build_kernel, dim3((unsigned)grid), dim3(kBlock), 0, stream, a, n,
+                       npad, m, W, wpad, G, pairs, tiles, per_xcd, idx, tie, any_tie);
     return hipGetLastError();
 }
 

@@ -92,6 +92,9 @@ ebic_status ensure_scratch(ebic_ctx *ctx, int64_t P) {
     return grow(ctx, ctx->d_acc, ctx->cap_P, P, true);
 }
 
+// The any-tie flag follows the m*m tie flags, 8-byte aligned.
+size_t tie_flag_offset(int32_t m) { return ((size_t)m * (size_t)m + 7) / 8 * 8; }
+
 int64_t index_bytes_for(int32_t m, int64_t wpad) {
     return (int64_t)m * (int64_t)m * (wpad * 8 + 1);  // order words + tie flags
 }
@@ -108,7 +111,7 @@ ebic_status build_index(ebic_ctx *ctx) {
                                                std::to_string(ctx->idx_bytes) + " bytes)");
         }
         ctx->d_idx = static_cast<uint64_t *>(p);
-        e = hipMalloc(&p, (size_t)ctx->m * (size_t)ctx->m);
+        e = hipMalloc(&p, tie_flag_offset(ctx->m) + sizeof(int32_t));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(ctx->d_idx);
@@ -121,18 +124,19 @@ ebic_status build_index(ebic_ctx *ctx) {
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+    int32_t *d_any = reinterpret_cast<int32_t *>(ctx->d_tie + tie_flag_offset(ctx->m));
     HIP_TRY(ctx, launch_index_build(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, ctx->wpad,
-                                    ctx->d_idx, ctx->d_tie, ctx->stream));
+                                    ctx->d_idx, ctx->d_tie, d_any, ctx->stream));
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // Whether any pair has a tied or unordered row (m*m bytes, once).
-    std::vector<uint8_t> flags((size_t)ctx->m * (size_t)ctx->m);
-    HIP_TRY(ctx, hipMemcpy(flags.data(), ctx->d_tie, flags.size(), hipMemcpyDeviceToHost));
-    ctx->any_tie = std::any_of(flags.begin(), flags.end(), [](uint8_t f) { return f != 0; });
+    // Whether two distinct columns have a tied or unordered row.
+    int32_t any = 1;
+    HIP_TRY(ctx, hipMemcpy(&any, d_any, sizeof(any), hipMemcpyDeviceToHost));
+    ctx->any_tie = any != 0;
     ctx->idx_ms = ms;
     ctx->idx_built = true;
     return EBIC_OK;
@@ -202,7 +206,7 @@ ebic_status create_common(const float *a, bool on_device, int64_t n_rows, int32_
     ctx->m = n_cols;
     ctx->W = words_of(n_rows);
     ctx->npad = ctx->W * 64;
-    ctx->wpad = (ctx->W + 7) / 8 * 8;
+    ctx->wpad = (ctx->W + 15) / 16 * 16;   // order rows start on 128-byte lines
     ctx->idx_bytes = index_bytes_for(n_cols, ctx->wpad);
 
     hipError_t e = hipSetDevice(device);

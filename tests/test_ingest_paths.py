@@ -1,0 +1,213 @@
+"""GPU: matrix ingest from every layout the ABI accepts (row-major and
+column-major, leading dimension beyond the row or column length, host and
+device sources), the pairwise order index checked word for word through
+every ordered column pair, tie detection, and the AUTO path's fall-back to
+the direct kernel when the index exceeds its budget.  Results are compared
+with the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[ingest] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_03039_amd as e
+    return e
+
+
+def _definition(a, series, *, sigma, max_violations, negative_trends):
+    """Masks, counts and Eq. (1) fitness by the NumPy formulation of the
+    trend test, which also applies to series that repeat a column (the C
+    oracle, like the host entry point, rejects those)."""
+    from oracle import brute
+    n = a.shape[0]
+    W = (n + 63) // 64
+    masks = np.zeros((len(series), 2, W), dtype=np.uint64)
+    counts = np.zeros(len(series), dtype=np.int32)
+    fit = np.zeros(len(series), dtype=np.float64)
+    for c, s in enumerate(series):
+        up, dn, cnt = brute.evaluate_series(a, s, max_violations, negative_trends)
+        for d, rows in enumerate((up, dn)):
+            bits = np.zeros(W * 64, dtype=bool)
+            bits[:n] = rows
+            masks[c, d] = np.packbits(bits, bitorder="little").view(np.uint64)
+        counts[c] = cnt
+        fit[c] = oracle.fitness(cnt, len(s), sigma)
+    return {"masks": masks, "counts": counts, "fitness": fit}
+
+
+def _views(a, pad=5):
+    """The same n x m matrix as row-major with ld = m + pad, column-major
+    (ld = n) and column-major with ld = n + pad."""
+    n, m = a.shape
+    wide = np.full((n, m + pad + 3), np.float32(7.5), dtype=np.float32)
+    wide[:, 3:3 + m] = a
+    rm = wide[:, 3:3 + m]
+    cm = np.asfortranarray(a)
+    tall = np.full((m, n + pad), np.float32(-2.5), dtype=np.float32)
+    tall[:, :n] = a.T
+    cm_ld = tall[:, :n].T
+    return {"row_ld": rm, "col": cm, "col_ld": cm_ld}
+
+
+def test_strided_layouts_are_read_in_place(E):
+    from paper_1801_03039_amd import binding as b
+    a = np.zeros((6, 4), dtype=np.float32)
+    v = _views(a)
+    assert b._strided_layout(v["row_ld"].shape, tuple(s // 4 for s in v["row_ld"].strides)) == \
+        (b.EBIC_ROW_MAJOR, 4 + 5 + 3)
+    assert b._strided_layout(v["col"].shape, tuple(s // 4 for s in v["col"].strides)) == \
+        (b.EBIC_COL_MAJOR, 6)
+    assert b._strided_layout(v["col_ld"].shape, tuple(s // 4 for s in v["col_ld"].strides)) == \
+        (b.EBIC_COL_MAJOR, 6 + 5)
+
+
+@pytest.mark.parametrize("n,m", [(1, 3), (70, 9), (1000, 33), (4097, 20)])
+@pytest.mark.parametrize("source", ["host", "device"])
+def test_ingest_layouts_match_oracle(E, n, m, source):
+    import torch
+    rng = np.random.default_rng(n * 31 + m)
+    a = synth.adversarial_matrix(rng, n, m)
+    pop = synth.random_population(rng, m, 120, 1, min(m, 9))
+    off, cols = synth.pack_cbf(pop)
+    kw = dict(sigma=5, max_violations=1, negative_trends=True)
+    ref = oracle.evaluate(a, off, cols, want_masks=True, **kw)
+    for name, view in _views(a).items():
+        src = view
+        if source == "device":
+            # the same strides on the device: a padded buffer, then the view
+            if name == "row_ld":
+                buf = torch.from_numpy(np.ascontiguousarray(view.base if view.base is not None
+                                                            else view)).cuda()
+                src = buf[:, 3:3 + m]
+            elif name == "col":
+                src = torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+            else:
+                buf = torch.from_numpy(np.ascontiguousarray(view.T.base)).cuda()
+                src = buf[:, :n].t()
+            assert tuple(src.shape) == (n, m)
+        for path in ("direct", "index"):
+            _note(f"ingest {source} {name} n={n} m={m} path={path}")
+            with E.Context(src, path=path) as ctx:
+                got = ctx.evaluate(off, cols, want_masks=True, **kw)
+            assert np.array_equal(got["counts"], ref["counts"])
+            assert np.array_equal(got["fitness"].view(np.int64), ref["fitness"].view(np.int64))
+            assert np.array_equal(got["masks"], ref["masks"])
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (65, 15), (1025, 16), (1100, 17), (3000, 40),
+                                 (16 * 64 * 3 + 1, 33)])
+@pytest.mark.parametrize("kind", ["normal", "adversarial"])
+def test_index_every_ordered_pair(E, n, m, kind):
+    # Series (p, q) for every ordered pair, p = q included: the rising mask
+    # is order row (p, q) of the index word for word, the falling mask
+    # order row (q, p).  Sizes cross the build's 1024-row blocks and its
+    # 16-column groups.
+    rng = np.random.default_rng(n + 7 * m)
+    a = (rng.standard_normal((n, m)).astype(np.float32) if kind == "normal"
+         else synth.adversarial_matrix(rng, n, m))
+    series = [[p, q] for p in range(m) for q in range(m)]
+    off, cols = synth.pack_cbf(series)
+    kw = dict(sigma=3, max_violations=0, negative_trends=True)
+    ref = _definition(a, series, **kw)
+    distinct = [i for i, (p, q) in enumerate(series) if p != q]
+    d_off, d_cols = synth.pack_cbf([series[i] for i in distinct])
+    ref_c = oracle.evaluate(a, d_off, d_cols, want_masks=True, **kw)
+    assert np.array_equal(ref["masks"][distinct], ref_c["masks"])
+    assert np.array_equal(ref["counts"][distinct], ref_c["counts"])
+    import torch
+    dev = torch.device("cuda:0")
+    with E.Context(a, path="index") as ctx:
+        _note(f"every pair {kind} n={n} m={m}")
+        P = len(series)
+        cnt = torch.empty(P, dtype=torch.int32, device=dev)
+        fit = torch.empty(P, dtype=torch.float64, device=dev)
+        masks = torch.empty((P, 2, ctx.W), dtype=torch.int64, device=dev)
+        # device entry point: no host check rejects the repeated column of (p, p)
+        ctx.evaluate_device(torch.from_numpy(off).to(dev), torch.from_numpy(cols).to(dev), cnt,
+                            fit, masks, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(masks.cpu().numpy().view(np.uint64), ref["masks"])
+        assert np.array_equal(cnt.cpu().numpy(), ref["counts"])
+        assert np.array_equal(fit.cpu().numpy().view(np.int64), ref["fitness"].view(np.int64))
+
+
+def test_tie_detection_and_repeated_columns(E):
+    # A matrix whose rows hold distinct values has no tied column pair (a
+    # column is not counted against itself); duplicating one column's value
+    # into another on one row makes it tied.  On the tie-free matrix the
+    # falling test takes lt(q,p) = ~lt(p,q), except for a repeated column:
+    # series with consecutive repeats still match the oracle on both paths.
+    import torch
+    rng = np.random.default_rng(11)
+    n, m = 3000, 24
+    a = np.stack([rng.permutation(m) for _ in range(n)]).astype(np.float32)
+    series = [[3, 3, 5], [1, 2, 2, 4], [7, 7], [9, 9, 9], [0, 5, 11, 11, 2], [4, 6, 8]]
+    series += synth.random_population(rng, m, 50, 2, 8)
+    off, cols = synth.pack_cbf(series)
+    dev = torch.device("cuda:0")
+    for k in (0, 1):
+        kw = dict(sigma=9, max_violations=k, negative_trends=True)
+        for tied in (False, True):
+            b = a.copy()
+            if tied:
+                b[1234, 17] = b[1234, 5]
+            ref_b = _definition(b, series, **kw)
+            with E.Context(b) as ctx:
+                for path in ("index", "direct"):
+                    ctx.set_path(path)
+                    if path == "index":
+                        assert ctx.info()["index_ties"] == int(tied)
+                    _note(f"ties={tied} k={k} path={path}")
+                    P = len(series)
+                    cnt = torch.empty(P, dtype=torch.int32, device=dev)
+                    fit = torch.empty(P, dtype=torch.float64, device=dev)
+                    masks = torch.empty((P, 2, ctx.W), dtype=torch.int64, device=dev)
+                    ctx.evaluate_device(torch.from_numpy(off).to(dev),
+                                        torch.from_numpy(cols).to(dev), cnt, fit, masks, **kw)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(cnt.cpu().numpy(), ref_b["counts"])
+                    assert np.array_equal(masks.cpu().numpy().view(np.uint64), ref_b["masks"])
+                    assert np.array_equal(fit.cpu().numpy().view(np.int64),
+                                          ref_b["fitness"].view(np.int64))
+
+
+def test_auto_falls_back_to_direct_over_budget(E):
+    rng = np.random.default_rng(12)
+    w = synth.WORKLOADS["expression"]
+    a, planted = synth.make_matrix(w)
+    pop = synth.mixed_population(rng, w, planted, 300)
+    off, cols = synth.pack_cbf(pop)
+    kw = dict(sigma=w.sigma, max_violations=1, negative_trends=True)
+    ref = oracle.evaluate(a, off, cols, want_masks=True, **kw)
+    with E.Context(a) as ctx:
+        need = ctx.info()["index_bytes"]
+        ctx.set_index_budget(need - 1)
+        _note("AUTO below the index size")
+        got = ctx.evaluate(off, cols, want_masks=True, **kw)
+        assert ctx.info()["index_built"] == 0
+        assert np.array_equal(got["counts"], ref["counts"])
+        assert np.array_equal(got["masks"], ref["masks"])
+        ctx.set_index_budget(need)
+        _note("AUTO at the index size")
+        got = ctx.evaluate(off, cols, want_masks=True, **kw)
+        assert ctx.info()["index_built"] == 1
+        assert np.array_equal(got["counts"], ref["counts"])
+        assert np.array_equal(got["fitness"].view(np.int64), ref["fitness"].view(np.int64))
+        # a budget lowered after the build sends AUTO back to the direct kernel
+        ctx.set_index_budget(0)
+        assert ctx.evaluate(off, cols, **kw)["counts"].tolist() == ref["counts"].tolist()
