@@ -87,8 +87,9 @@ typedef struct {
     int64_t index_bytes;      /* size of the index (built or prospective) */
     int64_t index_budget;     /* AUTO builds the index only within this many bytes */
     double index_build_ms;    /* device time of the last index build */
-    int32_t index_ties;       /* 1 if some column pair has a tied or unordered row (then
-                                 the falling test reads tie flags); valid once built */
+    int32_t index_ties;       /* 1 if two distinct columns have a tied or unordered row
+                                 (then the falling test reads tie flags); valid once
+                                 built */
 } ebic_ctx_info;
 
 /*
@@ -453,6 +454,9 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
 /* Device time (ms) of the last batched launch: the kernel, from events on
  * the batch's stream around its launch (the run table is copied before). */
 double ebic_batch_last_ms(const ebic_batch *b);
+/* Device time (ms) spent building the runs' pairwise order indexes at
+ * ebic_batch_create (sum over runs, from events around each build). */
+double ebic_batch_index_build_ms(const ebic_batch *b);
 /* Replays the last batched launch `reps` times back to back on the batch's
  * stream (same inputs, same results written again) and stores the mean
  * device time per launch in ms, from events around the replays: the

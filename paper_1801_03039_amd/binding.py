@@ -735,8 +735,9 @@ _batch_evaluate = _sig("ebic_batch_evaluate", _i32,
 _batch_evolve = _sig("ebic_batch_evolve", _i32,
                      [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _i32, _vp])
 _batch_last_ms = _sig("ebic_batch_last_ms", _dbl, [_vp])
+_batch_index_build_ms = _sig("ebic_batch_index_build_ms", _dbl, [_vp])
 _batch_time_replays = _sig("ebic_batch_time_replays", _i32, [_vp, _i32, _P(_dbl)])
-EXPORTED += ["ebic_batch_last_ms", "ebic_batch_time_replays", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
+EXPORTED += ["ebic_batch_last_ms", "ebic_batch_index_build_ms", "ebic_batch_time_replays", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
              "ebic_batch_set_tuning", "ebic_batch_evaluate", "ebic_batch_evolve"]
 
 
@@ -782,6 +783,10 @@ class Batch:
     def last_ms(self) -> float:
         """Device time (ms) of the last batched launch (the kernel)."""
         return float(_batch_last_ms(self._h))
+
+    def index_build_ms(self) -> float:
+        """Device ms spent building the runs' order indexes (sum over runs)."""
+        return float(_batch_index_build_ms(self._h))
 
     def time_replays(self, reps: int) -> float:
         """Mean device ms of ``reps`` back-to-back replays of the last launch."""

@@ -466,6 +466,13 @@ ebic_status ebic_batch_destroy(ebic_batch *b) {
 
 double ebic_batch_last_ms(const ebic_batch *b) { return b ? b->last_ms : 0.0; }
 
+double ebic_batch_index_build_ms(const ebic_batch *b) {
+    double ms = 0.0;
+    if (b)
+        for (const ebic_ctx *c : b->ctx) ms += c->idx_ms;
+    return ms;
+}
+
 ebic_status ebic_batch_time_replays(ebic_batch *b, int32_t reps, double *ms_per_launch) {
     if (!b || !ms_per_launch || reps < 1) return bfail(EBIC_E_ARG, "null argument or reps < 1");
     BHIP(hipSetDevice(b->device));
