@@ -473,6 +473,26 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
                               const ebic_evolve_params *params,
                               ebic_batch_generation_fn on_generation, void *user,
                               int32_t host_threads, ebic_result **results);
+/* The same runs with Steps 1-3 and 5 on the device (Section 2.2; the
+ * steps themselves are documented at ebic_evolve): one workgroup per run
+ * keeps the run's random stream, tabu list, top-rank list and penalties in
+ * device memory, so each generation is two launches on the batch's stream
+ * -- the steps, then the batched evaluation of all P members (elites are
+ * evaluated again; their scores are the same) -- with no host round trip.
+ * Results equal ebic_batch_evolve's run for run.  Limits (E_ARG beyond
+ * them): population <= 65535, len_max <= 58, tournament <= 31, n_cols <=
+ * 65535, and one run's state (previous population, penalties, top-rank
+ * list and its column index) within 160 KiB of LDS.  Device memory: a tabu
+ * table of 128-byte slots per run, 4 (generations + 1) P slots rounded up
+ * to a power of two.  on_generation (optional; it copies every generation
+ * back and synchronises) sees each running run's population after its
+ * evaluation.  In the stats, eval_ms is the device time of the whole
+ * generation loop (steps and evaluations) plus the Steps 6-7 evaluation.
+ * Errors: E_STATE if a run's tabu table fills up. */
+ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32_t generations,
+                                     const ebic_evolve_params *params,
+                                     ebic_batch_generation_fn on_generation, void *user,
+                                     ebic_result **results);
 
 /*
  * Surrogate fitness model for screening offspring: a 3-layer MLP over

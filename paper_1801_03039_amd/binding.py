@@ -734,10 +734,12 @@ _batch_evaluate = _sig("ebic_batch_evaluate", _i32,
                        [_vp, _vp, _vp, _vp, _P(Params), _vp, _vp, _vp, _i32])
 _batch_evolve = _sig("ebic_batch_evolve", _i32,
                      [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _i32, _vp])
+_batch_evolve_device = _sig("ebic_batch_evolve_device", _i32,
+                            [_vp, _vp, _i32, _P(EvolveParamsC), BATCH_GENERATION_FN, _vp, _vp])
 _batch_last_ms = _sig("ebic_batch_last_ms", _dbl, [_vp])
 _batch_index_build_ms = _sig("ebic_batch_index_build_ms", _dbl, [_vp])
 _batch_time_replays = _sig("ebic_batch_time_replays", _i32, [_vp, _i32, _P(_dbl)])
-EXPORTED += ["ebic_batch_last_ms", "ebic_batch_index_build_ms", "ebic_batch_time_replays", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
+EXPORTED += ["ebic_batch_evolve_device", "ebic_batch_last_ms", "ebic_batch_index_build_ms", "ebic_batch_time_replays", "ebic_batch_create", "ebic_batch_destroy", "ebic_batch_get_tuning",
              "ebic_batch_set_tuning", "ebic_batch_evaluate", "ebic_batch_evolve"]
 
 
@@ -851,9 +853,11 @@ class Batch:
         return out
 
     def evolve(self, seeds, generations: int, cfg: EvolveConfig, on_generation=None,
-               host_threads: int = 0):
+               host_threads: int = 0, device_steps: bool = False):
         """EBIC runs, one per matrix, seeds[r] for run r; returns one
-        EvolveResult per run.  ``on_generation(run, Generation)``."""
+        EvolveResult per run.  ``on_generation(run, Generation)``.
+        ``device_steps`` runs Steps 1-3 and 5 on the GPU
+        (``ebic_batch_evolve_device``); the runs are the same."""
         R = len(self.n_rows)
         sd = np.array([int(s) & ((1 << 64) - 1) for s in seeds], dtype=np.uint64)
         assert len(sd) == R
@@ -870,8 +874,12 @@ class Batch:
             gcb = BATCH_GENERATION_FN(cb)
         p = _params_c(cfg, GENERATION_FN())
         res = (ctypes.c_void_p * R)()
-        _check(_batch_evolve(self._h, sd.ctypes.data, int(generations), ctypes.byref(p), gcb, None,
-                             int(host_threads), res))
+        if device_steps:
+            _check(_batch_evolve_device(self._h, sd.ctypes.data, int(generations),
+                                        ctypes.byref(p), gcb, None, res))
+        else:
+            _check(_batch_evolve(self._h, sd.ctypes.data, int(generations), ctypes.byref(p), gcb,
+                                 None, int(host_threads), res))
         return [_finish(_vp(res[r]), self.n_rows[r]) for r in range(R)]
 
 

@@ -391,6 +391,73 @@ void parallel_for(int32_t n, int32_t threads, F &&f) {
     for (auto &th : pool) th.join();
 }
 
+// Steps 6-7 for every run in one launch (the listed series evaluated with
+// the expansion parameters and their row masks), then the runs' results.
+ebic_status finish_runs(ebic_batch *b, const ebic_evolve_params *params,
+                        const std::vector<std::vector<TopEntry>> &top,
+                        const std::vector<int32_t> &gens_run, const std::vector<int32_t> &stopped,
+                        int64_t evaluated, double eval_ms,
+                        std::chrono::steady_clock::time_point t0, ebic_result **results) {
+    const int32_t R = (int32_t)b->ctx.size();
+    ebic_params ex = params->expand;
+    ex.want_masks = 1;
+    Request q;
+    q.params = &ex;
+    q.masks = true;
+    q.P.assign((size_t)R, 0);
+    int64_t n_cols = 0, n_mask = 0;
+    std::vector<Pop> tops((size_t)R);
+    for (int32_t r = 0; r < R; ++r) {
+        for (const TopEntry &e : top[(size_t)r]) tops[(size_t)r].push(e.s.data(), (int32_t)e.s.size());
+        q.P[(size_t)r] = tops[(size_t)r].size();
+        q.n_cand += q.P[(size_t)r];
+        n_cols += tops[(size_t)r].off.back();
+        n_mask += (int64_t)q.P[(size_t)r] * 2 * b->ctx[(size_t)r]->W;
+    }
+    q.n_cols = n_cols;
+    ebic_status st = reserve(b, std::max<int64_t>(q.n_cand, 1), n_cols, std::max<int64_t>(n_mask, 1));
+    if (st != EBIC_OK) return st;
+    Packer pk{b};
+    b->h_off[0] = 0;
+    for (int32_t r = 0; r < R; ++r)
+        if (q.P[(size_t)r]) pk.add(tops[(size_t)r].off.data(), tops[(size_t)r].cols.data(), q.P[(size_t)r]);
+    const auto e0 = std::chrono::steady_clock::now();
+    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
+    std::vector<uint64_t> all_masks((size_t)std::max<int64_t>(n_mask, 1));
+    if (n_mask)
+        BHIP(hipMemcpy(all_masks.data(), b->d_masks, sizeof(uint64_t) * (size_t)n_mask,
+                       hipMemcpyDeviceToHost));
+    eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
+    evaluated += q.n_cand;
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int64_t cand = 0, mw = 0;
+    std::vector<ebic_result *> out((size_t)R, nullptr);
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t K = q.P[(size_t)r];
+        const int64_t W = b->ctx[(size_t)r]->W;
+        std::vector<uint64_t> m(all_masks.begin() + mw, all_masks.begin() + mw + (int64_t)K * 2 * W);
+        std::vector<int32_t> rc(b->h_counts + cand, b->h_counts + cand + K);
+        std::vector<double> rf(b->h_fit + cand, b->h_fit + cand + K);
+        out[(size_t)r] = make_result(top[(size_t)r], W, m, std::move(rc), std::move(rf));
+        if (!out[(size_t)r]) {
+            for (ebic_result *x : out) ebic_result_free(x);
+            return bfail(EBIC_E_NOMEM, "cannot allocate results");
+        }
+        ebic_run_stats &s = out[(size_t)r]->stats;
+        s.struct_size = sizeof(ebic_run_stats);
+        s.generations_run = gens_run[(size_t)r];
+        s.stopped_by_tabu = stopped[(size_t)r];
+        s.candidates_evaluated = evaluated;     // whole batch
+        s.wall_ms = wall;                       // whole batch
+        s.eval_ms = eval_ms;
+        s.host_ms = wall - eval_ms;
+        cand += K;
+        mw += (int64_t)K * 2 * W;
+    }
+    for (int32_t r = 0; r < R; ++r) results[r] = out[(size_t)r];
+    return EBIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -697,64 +764,256 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
         });
     }
 
-    // Steps 6-7 for every run in one launch, with masks.
-    ebic_params ex = params->expand;
-    ex.want_masks = 1;
-    Request q;
-    q.params = &ex;
-    q.masks = true;
-    q.P.assign((size_t)R, 0);
-    int64_t n_cols = 0, n_mask = 0;
-    std::vector<Pop> tops((size_t)R);
+    std::vector<std::vector<TopEntry>> tops((size_t)R);
+    std::vector<int32_t> gens((size_t)R), stopped((size_t)R);
     for (int32_t r = 0; r < R; ++r) {
-        for (const TopEntry &e : runs[(size_t)r]->top()) tops[(size_t)r].push(e.s.data(), (int32_t)e.s.size());
-        q.P[(size_t)r] = tops[(size_t)r].size();
-        q.n_cand += q.P[(size_t)r];
-        n_cols += tops[(size_t)r].off.back();
-        n_mask += (int64_t)q.P[(size_t)r] * 2 * b->ctx[(size_t)r]->W;
+        tops[(size_t)r] = runs[(size_t)r]->top();
+        gens[(size_t)r] = runs[(size_t)r]->generations_run();
+        stopped[(size_t)r] = runs[(size_t)r]->stopped() ? 1 : 0;
     }
-    q.n_cols = n_cols;
-    ebic_status st = reserve(b, std::max<int64_t>(q.n_cand, 1), n_cols, std::max<int64_t>(n_mask, 1));
-    if (st != EBIC_OK) return st;
-    Packer pk{b};
-    b->h_off[0] = 0;
-    for (int32_t r = 0; r < R; ++r)
-        if (q.P[(size_t)r]) pk.add(tops[(size_t)r].off.data(), tops[(size_t)r].cols.data(), q.P[(size_t)r]);
-    const auto e0 = std::chrono::steady_clock::now();
-    if (q.n_cand && (st = run_request(b, q, b->workgroups, b->unroll, b->words, b->whole)) != EBIC_OK) return st;
-    std::vector<uint64_t> all_masks((size_t)std::max<int64_t>(n_mask, 1));
-    if (n_mask)
-        BHIP(hipMemcpy(all_masks.data(), b->d_masks, sizeof(uint64_t) * (size_t)n_mask,
-                       hipMemcpyDeviceToHost));
-    eval_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - e0).count();
-    evaluated += q.n_cand;
-    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    int64_t cand = 0, mw = 0;
-    std::vector<ebic_result *> out((size_t)R, nullptr);
+    return finish_runs(b, params, tops, gens, stopped, evaluated, eval_ms, t0, results);
+}
+
+// Device-resident runs (Steps 1-3 and 5 in evolve_steps_kernel): each run
+// owns fixed slots -- candidates [r (P + 1), r (P + 1) + P) of the batched
+// launch and P * len_max column entries -- so that the run table, tile bases
+// and launch arguments stay the same from one generation to the next.
+ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32_t generations,
+                                     const ebic_evolve_params *params,
+                                     ebic_batch_generation_fn on_generation, void *user,
+                                     ebic_result **results) {
+    if (!b || !seeds || !params || !results) return bfail(EBIC_E_ARG, "null argument");
+    if (generations < 0) return bfail(EBIC_E_ARG, "generations must be >= 0");
+    const int32_t R = (int32_t)b->ctx.size();
+    int32_t max_m = 0;
     for (int32_t r = 0; r < R; ++r) {
-        const int32_t K = q.P[(size_t)r];
-        const int64_t W = b->ctx[(size_t)r]->W;
-        std::vector<uint64_t> m(all_masks.begin() + mw, all_masks.begin() + mw + (int64_t)K * 2 * W);
-        std::vector<int32_t> rc(b->h_counts + cand, b->h_counts + cand + K);
-        std::vector<double> rf(b->h_fit + cand, b->h_fit + cand + K);
-        out[(size_t)r] = make_result(runs[(size_t)r]->top(), W, m, std::move(rc), std::move(rf));
-        if (!out[(size_t)r]) {
-            for (ebic_result *x : out) ebic_result_free(x);
-            return bfail(EBIC_E_NOMEM, "cannot allocate results");
+        ebic_status st = check_params(params, b->ctx[(size_t)r]->n, b->ctx[(size_t)r]->m);
+        if (st != EBIC_OK) return st;
+        max_m = std::max(max_m, b->ctx[(size_t)r]->m);
+    }
+    if (params->eval.max_violations > kIndexMaxViolations ||
+        params->expand.max_violations > kIndexMaxViolations)
+        return bfail(EBIC_E_ARG, "batched runs support max_violations <= 3");
+    const int32_t P = params->population, slot = params->len_max, K = params->toplist_size;
+    if (P > 65535 || slot > 58 || params->tournament > 31 || max_m > 65535 || K > 32767)
+        return bfail(EBIC_E_ARG, "device steps need P <= 65535, len_max <= 58, tournament <= 31, "
+                                 "n_cols <= 65535, toplist_size <= 32767");
+    const int64_t lds = steps_lds_bytes(P, slot, max_m, K);
+    if (lds > 160 * 1024)
+        return bfail(EBIC_E_ARG, "device steps: the run's state does not fit in LDS (" +
+                                     std::to_string(lds) + " bytes)");
+    BHIP(hipSetDevice(b->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t stride = (int64_t)P + 1;          // candidate slots per run
+    const int64_t cslots = (int64_t)P * slot;       // column slots per run
+    const int64_t entries = (int64_t)P * (generations + 1);
+    uint64_t cap = 1024;
+    while (cap < 4ull * (uint64_t)entries) cap <<= 1;
+    const int64_t tab_n = (int64_t)P * slot * (slot + 1) / 2 + slot;
+
+    // device buffers, freed on every exit
+    std::vector<void *> bufs;
+    auto alloc = [&](void **p, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) bufs.push_back(*p);
+        return e;
+    };
+    struct Free {
+        std::vector<void *> &v;
+        ~Free() {
+            for (void *p : v) (void)hipFree(p);
         }
-        ebic_run_stats &s = out[(size_t)r]->stats;
-        s.struct_size = sizeof(ebic_run_stats);
-        s.generations_run = runs[(size_t)r]->generations_run();
-        s.stopped_by_tabu = runs[(size_t)r]->stopped() ? 1 : 0;
-        s.candidates_evaluated = evaluated;     // whole batch
-        s.wall_ms = wall;                       // whole batch
-        s.eval_ms = eval_ms;
-        s.host_ms = wall - eval_ms;
-        cand += K;
-        mw += (int64_t)K * 2 * W;
+    } free_all{bufs};
+    int32_t *d_off = nullptr, *d_cols = nullptr, *d_counts = nullptr, *d_top_cols = nullptr,
+            *d_top_len = nullptr, *d_top_cnt = nullptr;
+    double *d_fit = nullptr, *d_top_fit = nullptr, *d_pow = nullptr;
+    unsigned long long *d_acc = nullptr;
+    uint32_t *d_tabu = nullptr, *d_tile_base = nullptr;
+    StepsState *d_state = nullptr;
+    StepsRun *d_sruns = nullptr;
+    IndexRun *d_iruns = nullptr;
+    BHIP(alloc((void **)&d_off, sizeof(int32_t) * (size_t)(R * stride)));
+    BHIP(alloc((void **)&d_cols, sizeof(int32_t) * (size_t)(R * cslots)));
+    BHIP(alloc((void **)&d_counts, sizeof(int32_t) * (size_t)(R * stride)));
+    BHIP(alloc((void **)&d_fit, sizeof(double) * (size_t)(R * stride)));
+    BHIP(alloc((void **)&d_acc, sizeof(unsigned long long) * (size_t)(R * stride)));
+    BHIP(alloc((void **)&d_top_cols, sizeof(int32_t) * (size_t)R * K * slot));
+    BHIP(alloc((void **)&d_top_len, sizeof(int32_t) * (size_t)R * K));
+    BHIP(alloc((void **)&d_top_cnt, sizeof(int32_t) * (size_t)R * K));
+    BHIP(alloc((void **)&d_top_fit, sizeof(double) * (size_t)R * K));
+    BHIP(alloc((void **)&d_tabu, sizeof(uint32_t) * 32 * (size_t)cap * R));
+    BHIP(alloc((void **)&d_state, sizeof(StepsState) * (size_t)R));
+    BHIP(alloc((void **)&d_sruns, sizeof(StepsRun) * (size_t)R));
+    BHIP(alloc((void **)&d_pow, sizeof(double) * (size_t)tab_n));
+    BHIP(alloc((void **)&d_iruns, sizeof(IndexRun) * (size_t)R));
+    BHIP(alloc((void **)&d_tile_base, sizeof(uint32_t) * (size_t)(R + 1)));
+    BHIP(hipMemsetAsync(d_acc, 0, sizeof(unsigned long long) * (size_t)(R * stride), b->stream));
+    BHIP(hipMemsetAsync(d_tabu, 0, sizeof(uint32_t) * 32 * (size_t)cap * R, b->stream));
+    BHIP(hipMemsetAsync(d_off, 0, sizeof(int32_t) * (size_t)(R * stride), b->stream));
+
+    // base^(s / L) for 1 <= L <= len_max, 0 <= s <= L P: the doubles the
+    // host path computes with std::pow
+    std::vector<double> powtab((size_t)tab_n);
+    for (int32_t L = 1; L <= slot; ++L)
+        for (int64_t sum = 0; sum <= (int64_t)L * P; ++sum)
+            powtab[(size_t)((int64_t)P * L * (L - 1) / 2 + (L - 1) + sum)] =
+                std::pow(params->penalty_base, (double)sum / (double)L);
+    BHIP(hipMemcpyAsync(d_pow, powtab.data(), sizeof(double) * powtab.size(),
+                        hipMemcpyHostToDevice, b->stream));
+    std::vector<StepsState> states((size_t)R);
+    std::vector<StepsRun> sruns((size_t)R);
+    for (int32_t r = 0; r < R; ++r) {
+        states[(size_t)r] = StepsState{seeds[r], 0, 0, 0, 0, 0, 0, 0};
+        sruns[(size_t)r] = StepsRun{d_off + r * stride, d_cols + r * cslots, r * cslots,
+                                    d_counts + r * stride, d_fit + r * stride,
+                                    d_top_cols + (int64_t)r * K * slot, d_top_len + (int64_t)r * K,
+                                    d_top_cnt + (int64_t)r * K, d_top_fit + (int64_t)r * K,
+                                    d_tabu + (size_t)r * cap * 32, cap, d_state + r,
+                                    b->ctx[(size_t)r]->m, 0};
     }
-    for (int32_t r = 0; r < R; ++r) results[r] = out[(size_t)r];
-    return EBIC_OK;
+    BHIP(hipMemcpyAsync(d_state, states.data(), sizeof(StepsState) * (size_t)R,
+                        hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(d_sruns, sruns.data(), sizeof(StepsRun) * (size_t)R,
+                        hipMemcpyHostToDevice, b->stream));
+
+    // the evaluation's run table: P candidates per run at stride P + 1
+    const int32_t words = b->tuned ? b->words : 8;
+    const int32_t unroll = b->tuned ? b->unroll : 2;
+    const int32_t whole = b->tuned ? b->whole : 1;
+    std::vector<IndexRun> iruns((size_t)R);
+    std::vector<uint32_t> tile_base((size_t)R + 1);
+    uint64_t tiles = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        ebic_ctx *c = b->ctx[(size_t)r];
+        const uint64_t items = (uint64_t)((c->W + words - 1) / words);
+        const int32_t cpw = (whole && items <= 256) ? (int32_t)(256 / items) : 0;
+        iruns[(size_t)r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P,
+                                    r * stride, 0, cpw, 0};
+        tile_base[(size_t)r] = (uint32_t)tiles;
+        tiles += cpw ? ((uint64_t)P + cpw - 1) / cpw : ((uint64_t)P * items + 255) / 256;
+    }
+    tile_base[(size_t)R] = (uint32_t)tiles;
+    if (tiles > 0x7FFFFFFFull) return bfail(EBIC_E_ARG, "batched populations too large for one launch");
+    BHIP(hipMemcpyAsync(d_iruns, iruns.data(), sizeof(IndexRun) * (size_t)R, hipMemcpyHostToDevice,
+                        b->stream));
+    BHIP(hipMemcpyAsync(d_tile_base, tile_base.data(), sizeof(uint32_t) * (size_t)(R + 1),
+                        hipMemcpyHostToDevice, b->stream));
+    BatchLaunch L{};
+    L.runs = d_iruns;
+    L.tile_base = d_tile_base;
+    L.n_runs = R;
+    L.work = nullptr;
+    L.offsets = d_off;
+    L.cols = d_cols;
+    L.n_entries = R * cslots;
+    L.sigma = params->eval.sigma;
+    L.k = params->eval.max_violations;
+    L.negative = params->eval.negative_trends ? 1 : 0;
+    L.masks = nullptr;
+    L.acc = d_acc;
+    L.counts = d_counts;
+    L.fitness = d_fit;
+    L.grid = (uint32_t)tiles;
+    L.unroll = unroll;
+    L.words = words;
+
+    StepsArgs A{};
+    A.runs = d_sruns;
+    A.powtab = d_pow;
+    A.n_runs = R;
+    A.P = P;
+    A.len_min = params->len_min;
+    A.len_max = params->len_max;
+    A.slot = slot;
+    A.tournament = params->tournament;
+    A.wsum = 0;
+    for (int i = 0; i < 5; ++i) {
+        A.op_weight[i] = params->op_weight[i];
+        A.wsum += params->op_weight[i];
+    }
+    A.elite_num = params->elite_num;
+    A.elite_den = params->elite_den;
+    A.K = K;
+    A.tabu_limit = params->tabu_limit < 0 ? P : params->tabu_limit;
+    A.theta = params->overlap;
+    A.lds_bytes = (int32_t)lds;
+
+    // host copies for on_generation
+    std::vector<int32_t> h_off, h_cols, h_cnt;
+    std::vector<double> h_fit;
+    auto report = [&](int32_t gen) -> ebic_status {
+        if (!on_generation) return EBIC_OK;
+        BHIP(hipMemcpyAsync(states.data(), d_state, sizeof(StepsState) * (size_t)R,
+                            hipMemcpyDeviceToHost, b->stream));
+        h_off.resize((size_t)(R * stride));
+        h_cols.resize((size_t)(R * cslots));
+        h_cnt.resize((size_t)(R * stride));
+        h_fit.resize((size_t)(R * stride));
+        BHIP(hipMemcpyAsync(h_off.data(), d_off, sizeof(int32_t) * h_off.size(), hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(h_cols.data(), d_cols, sizeof(int32_t) * h_cols.size(), hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(h_cnt.data(), d_counts, sizeof(int32_t) * h_cnt.size(), hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipMemcpyAsync(h_fit.data(), d_fit, sizeof(double) * h_fit.size(), hipMemcpyDeviceToHost, b->stream));
+        BHIP(hipStreamSynchronize(b->stream));
+        std::vector<int32_t> off((size_t)P + 1);
+        for (int32_t r = 0; r < R; ++r) {
+            const StepsState &s = states[(size_t)r];
+            if (s.stopped || s.error || s.gen != gen) continue;
+            for (int32_t i = 0; i <= P; ++i)
+                off[(size_t)i] = h_off[(size_t)(r * stride + i)] - (int32_t)(r * cslots);
+            on_generation(user, r, gen, off.data(), h_cols.data() + r * cslots, P,
+                          h_cnt.data() + r * stride, h_fit.data() + r * stride);
+        }
+        return EBIC_OK;
+    };
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t &a, &b;
+        ~Ev() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev_guard{e0, e1};
+    BHIP(hipEventRecord(e0, b->stream));
+    ebic_status st;
+    for (int32_t g = 0; g <= generations; ++g) {
+        A.mode = g == 0 ? 0 : 1;
+        BHIP(launch_steps(A, b->stream));
+        BHIP(launch_eval_index_batch(L, b->stream));
+        if ((st = report(g)) != EBIC_OK) return st;
+    }
+    A.mode = 2;
+    BHIP(launch_steps(A, b->stream));
+    BHIP(hipEventRecord(e1, b->stream));
+    BHIP(hipEventSynchronize(e1));
+    float dev_ms = 0.f;
+    BHIP(hipEventElapsedTime(&dev_ms, e0, e1));
+
+    // the runs' top-rank lists
+    BHIP(hipMemcpy(states.data(), d_state, sizeof(StepsState) * (size_t)R, hipMemcpyDeviceToHost));
+    std::vector<int32_t> t_cols((size_t)R * K * slot), t_len((size_t)R * K), t_cnt((size_t)R * K);
+    std::vector<double> t_fit((size_t)R * K);
+    BHIP(hipMemcpy(t_cols.data(), d_top_cols, sizeof(int32_t) * t_cols.size(), hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(t_len.data(), d_top_len, sizeof(int32_t) * t_len.size(), hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(t_cnt.data(), d_top_cnt, sizeof(int32_t) * t_cnt.size(), hipMemcpyDeviceToHost));
+    BHIP(hipMemcpy(t_fit.data(), d_top_fit, sizeof(double) * t_fit.size(), hipMemcpyDeviceToHost));
+    std::vector<std::vector<TopEntry>> tops((size_t)R);
+    std::vector<int32_t> gens((size_t)R), stopped((size_t)R);
+    for (int32_t r = 0; r < R; ++r) {
+        const StepsState &s = states[(size_t)r];
+        if (s.error) return bfail(EBIC_E_STATE, "device steps: tabu table full in run " + std::to_string(r));
+        for (int32_t e = 0; e < s.n_top; ++e) {
+            const size_t at = (size_t)r * K + e;
+            const int32_t *c = t_cols.data() + at * slot;
+            tops[(size_t)r].push_back(TopEntry{std::vector<int32_t>(c, c + t_len[at]), t_cnt[at], t_fit[at]});
+        }
+        gens[(size_t)r] = s.gens_run;
+        stopped[(size_t)r] = s.stopped;
+    }
+    return finish_runs(b, params, tops, gens, stopped, (int64_t)R * P * (generations + 1),
+                       (double)dev_ms, t0, results);
 }
 
 }  // extern "C"

@@ -93,6 +93,55 @@ hipError_t launch_eval_index_batch(const BatchLaunch &b, hipStream_t stream);
 // Workgroups of the batch kernel resident per compute unit.
 int batch_wgs_per_cu();
 
+// Device-side evolution steps of batched runs (ebic_steps.hip): one
+// workgroup (one wave) per run carries Steps 1-3 and 5 of the run.
+//
+// Per-run state between launches, in device memory.
+struct StepsState {
+    uint64_t rng;        // SplitMix64 state
+    int32_t gen;         // generation of the population in the run's CBF slots
+    int32_t n_top;       // entries of the top-rank list
+    int32_t first_new;   // elites at the head of the population
+    int32_t stopped;     // the tabu rule ended the run
+    int32_t gens_run;    // generations completed after Step 1
+    int32_t error;       // 1: the tabu table is full (the run stops)
+    int64_t tabu_used;   // series in the tabu table
+};
+
+// One run's buffers (device pointers).
+struct StepsRun {
+    int32_t *off;          // P + 1 offsets: global indices into the batch's column array
+    int32_t *cols;         // the run's P * slot column slots (cols[0] is global index col_base)
+    int64_t col_base;
+    const int32_t *counts; // evaluation outputs of the run's P members
+    const double *fit;
+    int32_t *top_cols;     // K * slot columns of the top-rank list
+    int32_t *top_len;      // K
+    int32_t *top_cnt;      // K
+    double *top_fit;       // K
+    uint32_t *tabu;        // tabu_cap slots of 32 dwords
+    uint64_t tabu_cap;     // power of two
+    StepsState *state;
+    int32_t m;             // matrix columns
+    int32_t pad;
+};
+
+struct StepsArgs {
+    const StepsRun *runs;
+    const double *powtab;  // penalty_base^(s/L) at P*L*(L-1)/2 + (L-1) + s, s <= L*P
+    int32_t n_runs, mode;  // mode 0: Step 1; 1: Step 5 then Steps 2-3; 2: Step 5
+    int32_t P, len_min, len_max, slot;   // slot >= len_max: column slots per series
+    int32_t tournament, wsum, elite_num, elite_den, K, tabu_limit;
+    int32_t op_weight[5];
+    int32_t lds_bytes;
+    double theta;
+};
+
+// Dynamic LDS bytes a steps launch needs for P members, `slot` column slots,
+// m columns and a top-rank list of K.
+int64_t steps_lds_bytes(int32_t P, int32_t slot, int32_t m, int32_t K);
+hipError_t launch_steps(const StepsArgs &a, hipStream_t stream);
+
 // Device-pointer evaluation (ebic_runtime.cpp).  acc == nullptr: the
 // context's own accumulators, grown on demand, and the order index built on
 // first need.  Otherwise acc holds >= P zeroed accumulators and nothing is
