@@ -336,6 +336,14 @@ def run_batched(args):
                          "wall_ms": round((time.perf_counter() - t0) * 1e3, 1),
                          "eval_ms": round(res[0].stats["eval_ms"], 1),
                          "candidates_evaluated": res[0].stats["candidates_evaluated"]}
+        log(f"batched: {R} EBIC runs x {G} generations, steps on the device")
+        t0 = time.perf_counter()
+        res_d = b.evolve(list(range(R)), G, cfg, device_steps=True)
+        out["evolve_device_steps"] = {
+            "wall_ms": round((time.perf_counter() - t0) * 1e3, 1),
+            "device_ms": round(res_d[0].stats["eval_ms"], 1),
+            "same_runs": all([x["cols"] for x in h.biclusters] == [x["cols"] for x in d.biclusters]
+                             for h, d in zip(res, res_d))}
     if not args.no_cpu:
         import oracle
         cores = oracle.max_threads()
@@ -624,7 +632,27 @@ def batched_subresult(args):
         call_ms = (time.perf_counter() - t0) * 1e3 / n_calls
         dev_ms = b.time_replays(max(args.steps // 10, 20))
         tuning = b.tuning()
-    G = 100
+        G = 100
+        evolve = None
+        if not args.no_evolve:
+            # the 64 runs for G generations, Steps 1-3 and 5 on the host
+            # threads, then on the device; the two must give the same runs
+            cfg = ebic.EvolveConfig(population=1024, len_min=3, len_max=20,
+                                    eval=ebic.Trend(25), expand=ebic.Trend(25, 0, True))
+            evolve = {"generations": G}
+            res = {}
+            for dev in (False, True):
+                t0 = time.perf_counter()
+                res[dev] = b.evolve(list(range(R)), G, cfg, device_steps=dev)
+                wall = (time.perf_counter() - t0) * 1e3
+                key = "device_steps" if dev else "host_steps"
+                evolve[key] = {"wall_ms": round(wall, 1),
+                               "ms_per_generation": round(wall / (G + 1), 4),
+                               "device_ms": round(res[dev][0].stats["eval_ms"], 1)}
+            evolve["same_runs"] = all(
+                [x["cols"] for x in h.biclusters] == [x["cols"] for x in d.biclusters]
+                and [x["fitness"] for x in h.biclusters] == [x["fitness"] for x in d.biclusters]
+                for h, d in zip(res[False], res[True]))
     return {
         "workload": f"batched: {R} runs, rows log-uniform 500-50000, cols 20-1000, N(0,1), "
                     f"P=1024 each, L 3-20, rising, k=0, sigma=25",
@@ -638,6 +666,7 @@ def batched_subresult(args):
         "value_amortized": round(amortized(checks, dev_ms, build_ms, G), 3),
         "amortized_over_generations": G,
         "tuning": tuning,
+        "evolve": evolve,
     }
 
 

@@ -482,9 +482,10 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
  * Results equal ebic_batch_evolve's run for run.  Limits (E_ARG beyond
  * them): population <= 65535, len_max <= 58, tournament <= 31, n_cols <=
  * 65535, and one run's state (previous population, penalties, top-rank
- * list and its column index) within 160 KiB of LDS.  Device memory: a tabu
- * table of 128-byte slots per run, 4 (generations + 1) P slots rounded up
- * to a power of two.  on_generation (optional; it copies every generation
+ * list and its column index) within 160 KiB of LDS, operation weights
+ * summing below 2^31.  Device memory per run: a tabu table of 16-byte slots
+ * (2 (generations + 1) P rounded up to a power of two) and an arena of
+ * (generations + 1) P len_max 16-bit columns.  on_generation (optional; it copies every generation
  * back and synchronises) sees each running run's population after its
  * evaluation.  In the stats, eval_ms is the device time of the whole
  * generation loop (steps and evaluations) plus the Steps 6-7 evaluation.

@@ -795,9 +795,13 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
         params->expand.max_violations > kIndexMaxViolations)
         return bfail(EBIC_E_ARG, "batched runs support max_violations <= 3");
     const int32_t P = params->population, slot = params->len_max, K = params->toplist_size;
-    if (P > 65535 || slot > 58 || params->tournament > 31 || max_m > 65535 || K > 32767)
+    int64_t wsum = 0;
+    for (int i = 0; i < 5; ++i) wsum += params->op_weight[i];
+    if (P > 65535 || slot > 58 || params->tournament > 31 || max_m > 65535 || K > 32767 ||
+        wsum > INT32_MAX)
         return bfail(EBIC_E_ARG, "device steps need P <= 65535, len_max <= 58, tournament <= 31, "
-                                 "n_cols <= 65535, toplist_size <= 32767");
+                                 "n_cols <= 65535, toplist_size <= 32767, operation weights "
+                                 "summing below 2^31");
     const int64_t lds = steps_lds_bytes(P, slot, max_m, K);
     if (lds > 160 * 1024)
         return bfail(EBIC_E_ARG, "device steps: the run's state does not fit in LDS (" +
@@ -808,7 +812,8 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
     const int64_t cslots = (int64_t)P * slot;       // column slots per run
     const int64_t entries = (int64_t)P * (generations + 1);
     uint64_t cap = 1024;
-    while (cap < 4ull * (uint64_t)entries) cap <<= 1;
+    while (cap < 2ull * (uint64_t)entries) cap <<= 1;
+    const int64_t arena_cap = entries * slot;
     const int64_t tab_n = (int64_t)P * slot * (slot + 1) / 2 + slot;
 
     // device buffers, freed on every exit
@@ -829,6 +834,7 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
     double *d_fit = nullptr, *d_top_fit = nullptr, *d_pow = nullptr;
     unsigned long long *d_acc = nullptr;
     uint32_t *d_tabu = nullptr, *d_tile_base = nullptr;
+    uint16_t *d_arena = nullptr;
     StepsState *d_state = nullptr;
     StepsRun *d_sruns = nullptr;
     IndexRun *d_iruns = nullptr;
@@ -841,14 +847,15 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
     BHIP(alloc((void **)&d_top_len, sizeof(int32_t) * (size_t)R * K));
     BHIP(alloc((void **)&d_top_cnt, sizeof(int32_t) * (size_t)R * K));
     BHIP(alloc((void **)&d_top_fit, sizeof(double) * (size_t)R * K));
-    BHIP(alloc((void **)&d_tabu, sizeof(uint32_t) * 32 * (size_t)cap * R));
+    BHIP(alloc((void **)&d_tabu, sizeof(uint32_t) * 4 * (size_t)cap * R));
+    BHIP(alloc((void **)&d_arena, sizeof(uint16_t) * (size_t)arena_cap * R));
     BHIP(alloc((void **)&d_state, sizeof(StepsState) * (size_t)R));
     BHIP(alloc((void **)&d_sruns, sizeof(StepsRun) * (size_t)R));
     BHIP(alloc((void **)&d_pow, sizeof(double) * (size_t)tab_n));
     BHIP(alloc((void **)&d_iruns, sizeof(IndexRun) * (size_t)R));
     BHIP(alloc((void **)&d_tile_base, sizeof(uint32_t) * (size_t)(R + 1)));
     BHIP(hipMemsetAsync(d_acc, 0, sizeof(unsigned long long) * (size_t)(R * stride), b->stream));
-    BHIP(hipMemsetAsync(d_tabu, 0, sizeof(uint32_t) * 32 * (size_t)cap * R, b->stream));
+    BHIP(hipMemsetAsync(d_tabu, 0, sizeof(uint32_t) * 4 * (size_t)cap * R, b->stream));
     BHIP(hipMemsetAsync(d_off, 0, sizeof(int32_t) * (size_t)(R * stride), b->stream));
 
     // base^(s / L) for 1 <= L <= len_max, 0 <= s <= L P: the doubles the
@@ -868,7 +875,8 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
                                     d_counts + r * stride, d_fit + r * stride,
                                     d_top_cols + (int64_t)r * K * slot, d_top_len + (int64_t)r * K,
                                     d_top_cnt + (int64_t)r * K, d_top_fit + (int64_t)r * K,
-                                    d_tabu + (size_t)r * cap * 32, cap, d_state + r,
+                                    d_tabu + (size_t)r * cap * 4, cap,
+                                    d_arena + (size_t)r * arena_cap, arena_cap, d_state + r,
                                     b->ctx[(size_t)r]->m, 0};
     }
     BHIP(hipMemcpyAsync(d_state, states.data(), sizeof(StepsState) * (size_t)R,
@@ -1003,7 +1011,7 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
     std::vector<int32_t> gens((size_t)R), stopped((size_t)R);
     for (int32_t r = 0; r < R; ++r) {
         const StepsState &s = states[(size_t)r];
-        if (s.error) return bfail(EBIC_E_STATE, "device steps: tabu table full in run " + std::to_string(r));
+        if (s.error) return bfail(EBIC_E_STATE, "device steps: tabu table or arena full in run " + std::to_string(r));
         for (int32_t e = 0; e < s.n_top; ++e) {
             const size_t at = (size_t)r * K + e;
             const int32_t *c = t_cols.data() + at * slot;

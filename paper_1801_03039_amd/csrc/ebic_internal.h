@@ -104,8 +104,8 @@ struct StepsState {
     int32_t first_new;   // elites at the head of the population
     int32_t stopped;     // the tabu rule ended the run
     int32_t gens_run;    // generations completed after Step 1
-    int32_t error;       // 1: the tabu table is full (the run stops)
-    int64_t tabu_used;   // series in the tabu table
+    int32_t error;       // 1: the tabu table or its arena is full (the run stops)
+    int64_t arena_used;  // columns stored in the tabu arena
 };
 
 // One run's buffers (device pointers).
@@ -119,8 +119,10 @@ struct StepsRun {
     int32_t *top_len;      // K
     int32_t *top_cnt;      // K
     double *top_fit;       // K
-    uint32_t *tabu;        // tabu_cap slots of 32 dwords
+    uint32_t *tabu;        // tabu_cap slots of 4 dwords {tag lo, tag hi, arena offset, length}
     uint64_t tabu_cap;     // power of two
+    uint16_t *arena;       // columns of the listed series
+    int64_t arena_cap;
     StepsState *state;
     int32_t m;             // matrix columns
     int32_t pad;

@@ -20,8 +20,8 @@
 //     weaker entries it overlaps by more than theta; stable sort, cut to K.
 //     The pass stops once K live entries have fitness >= f(x): no later
 //     member can change the first K.
-// The tabu list is an open-addressing hash table of whole series (exact
-// comparison), one 128-byte slot per series.
+// The tabu list is an open-addressing hash table of 16-byte slots over an
+// arena of the listed series (exact comparison).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -33,8 +33,6 @@ namespace {
 
 constexpr int kLanes = 64;
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-constexpr int kSlotDwords = 32;          // tabu slot: tag (2), length (1), 2 columns per dword
-constexpr int kMaxSlotCols = 2 * (kSlotDwords - 3);
 enum { OP_INSERT = 0, OP_DELETE, OP_SWAP, OP_SUBSTITUTE, OP_CROSSOVER };
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -44,6 +42,12 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+// The workgroup is one wave: its LDS operations are performed in program
+// order, so lanes only need the compiler not to move memory operations
+// across this point (no s_barrier, and no wait for outstanding global
+// stores as a workgroup barrier's fence would do).
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 __device__ __forceinline__ int32_t rl32(int32_t v, int lane) {
     return __builtin_amdgcn_readlane(v, lane);
@@ -62,6 +66,18 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// x % n.  For n < 2^16 the 64-bit value is reduced Horner-style in 16-bit
+// digits with three 32-bit remainders (each partial value stays below
+// 2^32), much shorter than a 64-bit division.
+__device__ __forceinline__ uint32_t mod_u64(uint64_t x, uint32_t n) {
+    if (n <= 0xFFFFu) {
+        uint32_t r = (uint32_t)(x >> 32) % n;
+        r = ((r << 16) | (uint32_t)((x >> 16) & 0xFFFFu)) % n;
+        return ((r << 16) | (uint32_t)(x & 0xFFFFu)) % n;
+    }
+    return (uint32_t)(x % (uint64_t)n);
+}
+
 // A window of the next 64 SplitMix64 outputs: lane i holds output used+1+i
 // relative to `base` (which already excludes the consumed ones); uniform
 // `used` counts the outputs consumed from the window.
@@ -69,11 +85,24 @@ struct Draws {
     uint64_t base;   // generator state at the window start
     uint64_t raw;    // this lane's output: mix(base + (lane + 1) * gamma)
     int used;
+    // this lane's output reduced modulo the run's fixed bounds (the
+    // population size, the operation weight sum and the column count),
+    // computed once per window
+    uint32_t nP, nW, nM;
+    uint32_t modP, modW, modM;
 
-    __device__ void fill() { raw = mix64(base + (uint64_t)(lane_id() + 1) * kGamma); }
-    __device__ void start(uint64_t state) {
+    __device__ void fill() {
+        raw = mix64(base + (uint64_t)(lane_id() + 1) * kGamma);
+        modP = mod_u64(raw, nP);
+        modW = mod_u64(raw, nW);
+        modM = mod_u64(raw, nM);
+    }
+    __device__ void start(uint64_t state, uint32_t P, uint32_t W, uint32_t M) {
         base = state;
         used = 0;
+        nP = P;
+        nW = W;
+        nM = M;
         fill();
     }
     // At least n (<= 64) unconsumed outputs in the window.
@@ -87,11 +116,16 @@ struct Draws {
     __device__ uint64_t state() const { return base + (uint64_t)used * kGamma; }
     // Unconsumed output k (uniform k, used + k < 64).
     __device__ uint64_t at(int k) const { return rl64(raw, used + k); }
-    __device__ uint32_t below(uint64_t n) {
+    __device__ uint32_t below(uint32_t n) {
         need(1);
         const uint64_t r = at(0);
         ++used;
-        return (uint32_t)(r % n);
+        return mod_u64(r, n);
+    }
+    // A draw in [0, M) (the column count).
+    __device__ uint32_t below_m() {
+        need(1);
+        return (uint32_t)rl32((int32_t)modM, used++);
     }
 };
 
@@ -111,13 +145,14 @@ struct Lds {
     uint16_t *erank;    // K: entry at each rank of the updated list
     uint64_t *colmask;  // m * EW: bit e of column c's words when entry e holds c
     int32_t *cbuf;      // 64: crossover scratch
+    uint32_t *tsum;     // 64: tournament penalty sums
 };
 
 __host__ __device__ inline int64_t align16(int64_t x) { return (x + 15) & ~int64_t(15); }
 
 struct LdsShape {
-    int32_t P, P2, slot, m, K, E, EW;
-    int64_t off[14];
+    int32_t P, P2, slot, pstride, m, K, E, EW;
+    int64_t off[15];
     int64_t total;
 };
 
@@ -127,16 +162,17 @@ __host__ __device__ inline LdsShape lds_shape(int32_t P, int32_t slot, int32_t m
     s.P2 = 1;
     while (s.P2 < P) s.P2 <<= 1;
     s.slot = slot;
+    s.pstride = (slot + 1) & ~1;   // even: a series row is whole dwords
     s.m = m;
     s.K = K;
     s.E = 2 * K;
     s.EW = (s.E + 63) / 64;
-    const int64_t sizes[14] = {
-        (int64_t)P * slot * 2, P, (int64_t)P * 8, (int64_t)P * 4, (int64_t)m * 4,
+    const int64_t sizes[15] = {
+        (int64_t)P * s.pstride * 2, P, (int64_t)P * 8, (int64_t)P * 4, (int64_t)m * 4,
         (int64_t)s.P2 * 2, (int64_t)s.E * slot * 2, s.E, s.E, (int64_t)s.E * 8,
-        (int64_t)s.E * 4, (int64_t)K * 2, (int64_t)m * s.EW * 8, 64 * 4};
+        (int64_t)s.E * 4, (int64_t)K * 2, (int64_t)m * s.EW * 8, 64 * 4, 64 * 4};
     int64_t at = 0;
-    for (int i = 0; i < 14; ++i) {
+    for (int i = 0; i < 15; ++i) {
         s.off[i] = at;
         at = align16(at + sizes[i]);
     }
@@ -160,6 +196,7 @@ __device__ inline Lds lds_map(unsigned char *base, const LdsShape &s) {
     L.erank = (uint16_t *)(base + s.off[11]);
     L.colmask = (uint64_t *)(base + s.off[12]);
     L.cbuf = (int32_t *)(base + s.off[13]);
+    L.tsum = (uint32_t *)(base + s.off[14]);
     return L;
 }
 
@@ -171,62 +208,74 @@ __device__ __forceinline__ bool series_has(int32_t ch, int32_t L, int32_t c) {
 }
 
 // A column not in the series ch[0, L): draws c = next() % M until one is
-// new (the draws of one window are tested in parallel, the first new one
-// wins and the draws up to it are consumed).
+// new.  Usually the first draw is (L < M), so draws are tested one at a
+// time, each against every lane of the series at once.
 __device__ int32_t new_column(Draws &d, int32_t ch, int32_t L, int32_t M) {
     const int lane = lane_id();
     for (;;) {
-        d.need(1);
-        const int avail = kLanes - d.used;
-        const uint64_t r = shfl64(d.raw, min(d.used + lane, kLanes - 1));
-        const int32_t c = (int32_t)(r % (uint64_t)M);
-        const bool ok = lane < avail && !series_has(ch, L, c);
-        const uint64_t b = __ballot(ok);
-        if (b) {
-            const int f = __ffsll((unsigned long long)b) - 1;
-            d.used += f + 1;
-            return rl32(c, f);
-        }
-        d.used += avail;
+        const int32_t c = (int32_t)d.below_m();
+        if (__ballot(lane < L && ch == c) == 0ull) return c;
     }
 }
 
-// Tabu-list slot image of the series ch[0, L) held by lane t < 32 (dword t):
-// tag (2 dwords), length, then the columns two per dword.
-__device__ __forceinline__ uint32_t slot_image(int32_t ch, int32_t L, uint64_t tag) {
-    const int lane = lane_id();
-    const int k = max(lane - 3, 0);
-    const int32_t c0 = __shfl(ch, min(2 * k, kLanes - 1));
-    const int32_t c1 = __shfl(ch, min(2 * k + 1, kLanes - 1));
-    const uint32_t lo = 2 * k < L ? ((uint32_t)c0 & 0xFFFFu) : 0u;
-    const uint32_t hi = 2 * k + 1 < L ? ((uint32_t)c1 & 0xFFFFu) : 0u;
-    if (lane == 0) return (uint32_t)tag;
-    if (lane == 1) return (uint32_t)(tag >> 32);
-    if (lane == 2) return (uint32_t)L;
-    return lane < kSlotDwords ? (lo | (hi << 16)) : 0u;
+// XOR of x over the wave's 64 lanes: DPP exchanges inside each row of 16
+// lanes (adjacent lanes, lane pairs, half-row mirror, row mirror), then the
+// four row values.
+__device__ __forceinline__ uint32_t wave_xor(uint32_t x) {
+    x ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xb1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+    x ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4e, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+    x ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    x ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xf, 0xf, false);  // row_mirror
+    return (uint32_t)(rl32((int32_t)x, 0) ^ rl32((int32_t)x, 16) ^ rl32((int32_t)x, 32) ^
+                      rl32((int32_t)x, 48));
 }
 
-// Inserts the series ch[0, L) into the run's tabu table; false if it is
-// already there.  *full is set when no slot is left.
-__device__ bool tabu_insert(const StepsRun &R, int32_t ch, int32_t L, bool *full) {
+// Tabu list: open addressing with linear probing over 16-byte slots {tag
+// (two dwords, never 0 when used), arena offset, length}; the series
+// themselves are appended to the run's arena (16-bit columns).  A probe
+// reads 8 consecutive slots at once (one lane each); a tag match is
+// confirmed against the stored series, so membership is exact.  Inserts
+// the series ch[0, L) and returns true, or returns false if it is already
+// listed.  *full is set when the table or the arena has no room left.
+__device__ bool tabu_insert(const StepsRun &R, int64_t &arena_used, int32_t ch, int32_t L,
+                            bool *full) {
     const int lane = lane_id();
-    uint64_t v = lane < L ? mix64(((uint64_t)(uint32_t)ch << 8) ^ (uint64_t)lane ^
-                                  ((uint64_t)L << 40) ^ 0x5851F42D4C957F2Dull)
-                          : 0ull;
-    for (int o = 32; o > 0; o >>= 1) v += shfl64(v, lane ^ o);
-    const uint64_t tag = mix64(rl64(v, 0)) | 1ull;
-    const uint32_t img = slot_image(ch, L, tag);
+    const uint64_t v = lane < L ? mix64(((uint64_t)(uint32_t)ch << 8) ^ (uint64_t)lane ^
+                                        ((uint64_t)L << 40) ^ 0x5851F42D4C957F2Dull)
+                                : 0ull;
+    const uint64_t h = ((uint64_t)wave_xor((uint32_t)(v >> 32)) << 32) | wave_xor((uint32_t)v);
+    const uint64_t tag = mix64(h) | 1ull;
+    const uint32_t tlo = (uint32_t)tag, thi = (uint32_t)(tag >> 32);
     const uint64_t mask = R.tabu_cap - 1;
-    uint64_t slot = (tag >> 1) & mask;
-    for (uint64_t probe = 0; probe < R.tabu_cap; ++probe) {
-        uint32_t *sp = R.tabu + slot * kSlotDwords;
-        const uint32_t w = lane < kSlotDwords ? sp[lane] : 0u;
-        if (rl32((int32_t)w, 0) == 0) {       // empty slot: the series is new
-            if (lane < kSlotDwords) sp[lane] = img;
+    uint64_t s0 = (tag >> 1) & mask;
+    for (uint64_t seen = 0; seen < R.tabu_cap;) {
+        const uint64_t my = (s0 + (uint64_t)lane) & mask;
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (lane < 8) w = reinterpret_cast<const uint4 *>(R.tabu)[my];
+        const bool empty = w.x == 0u;
+        const bool match = w.x == tlo && w.y == thi && (int32_t)w.w == L;
+        const uint64_t hit = __ballot(lane < 8 && (empty || match));
+        if (hit == 0ull) {
+            s0 = (s0 + 8) & mask;
+            seen += 8;
+            continue;
+        }
+        const int f = __ffsll((unsigned long long)hit) - 1;
+        if (rl32((int32_t)w.x, f) == 0) {      // an empty slot first: the series is new
+            if (arena_used + L > R.arena_cap) break;
+            if (lane == f)
+                reinterpret_cast<uint4 *>(R.tabu)[my] =
+                    make_uint4(tlo, thi, (uint32_t)arena_used, (uint32_t)L);
+            if (lane < L) R.arena[arena_used + lane] = (uint16_t)ch;
+            arena_used += L;
             return true;
         }
-        if (__ballot(lane < kSlotDwords && w != img) == 0ull) return false;
-        slot = (slot + 1) & mask;
+        // tag and length match: compare the stored series
+        const uint32_t at = (uint32_t)rl32((int32_t)w.z, f);
+        const bool same = __ballot(lane < L && (int32_t)R.arena[at + lane] != ch) == 0ull;
+        if (same) return false;
+        s0 = (s0 + (uint64_t)f + 1) & mask;
+        seen += (uint64_t)f + 1;
     }
     *full = true;
     return false;
@@ -234,37 +283,57 @@ __device__ bool tabu_insert(const StepsRun &R, int32_t ch, int32_t L, bool *full
 
 // Tournament draws: lane t < nsets*T takes output used + set*(T+1) + j of
 // the window (set = t / T, j = t % T) and computes its member and adjusted
-// quality.
+// quality.  The penalty sums of all draws are gathered at once: lane g of
+// a grid over (draw, dword of the draw's series row, two columns per
+// dword) adds its columns' penalties into the draw's LDS sum.
 __device__ void tournament_lanes(const Draws &d, int nsets, int T, int32_t P, const Lds &S,
-                                 int32_t slot, const double *__restrict__ powtab, int32_t &idx,
-                                 double &adj) {
+                                 int32_t pstride, const double *__restrict__ powtab,
+                                 int32_t &idx, double &adj) {
     const int lane = lane_id();
     const int set = lane / T, j = lane - set * T;
+    const int nd = nsets * T;
     const bool act = set < nsets;
-    const uint64_t r = shfl64(d.raw, act ? d.used + set * (T + 1) + j : 0);
-    idx = act ? (int32_t)(r % (uint64_t)P) : 0;
+    const int32_t mp = __shfl((int32_t)d.modP, act ? d.used + set * (T + 1) + j : 0);
+    idx = act ? mp : 0;
+    const int32_t L = act ? (int32_t)S.plen[idx] : 0;
+    if (lane < nd) S.tsum[lane] = 0u;
+    wave_sync();
+    const int dw = pstride / 2;                  // dwords per series row
+    for (int base = 0; base < nd * dw; base += kLanes) {
+        const int g = base + lane;
+        const int dd = g / dw, q = g - dd * dw;
+        const int32_t id = __shfl(idx, min(dd, kLanes - 1));
+        const int32_t Ld = __shfl(L, min(dd, kLanes - 1));
+        if (dd < nd && 2 * q < Ld) {
+            const uint32_t w =
+                reinterpret_cast<const uint32_t *>(S.pcols + (int64_t)id * pstride)[q];
+            uint32_t sum = S.pen[w & 0xFFFFu];
+            if (2 * q + 1 < Ld) sum += S.pen[w >> 16];
+            atomicAdd(&S.tsum[dd], sum);
+        }
+    }
+    wave_sync();
     adj = -INFINITY;
     if (act) {
-        const int32_t L = S.plen[idx];
-        int64_t sum = 0;
-        for (int32_t t = 0; t < L; ++t) sum += S.pen[S.pcols[idx * slot + t]];
+        const int64_t sum = S.tsum[lane];
         const double pw = powtab[(int64_t)P * L * (L - 1) / 2 + (L - 1) + sum];
         adj = S.pfit[idx] / pw;
     }
 }
 
-// The first strictly best draw among lanes [first, first + T).
+// The first strictly best draw among lanes [first, first + T): the lane
+// whose quality beats every earlier draw and is at least every later one
+// (all lanes test this at once).
 __device__ int32_t tournament_winner(int32_t idx, double adj, int first, int T) {
-    int32_t best = -1;
-    double best_adj = -INFINITY;
+    const int lane = lane_id();
+    const int t = lane - first;
+    bool win = t >= 0 && t < T;
     for (int j = 0; j < T; ++j) {
         const double a = rlf64(adj, first + j);
-        if (a > best_adj) {
-            best_adj = a;
-            best = rl32(idx, first + j);
-        }
+        win &= j < t ? adj > a : (j > t ? adj >= a : true);
     }
-    return best;
+    const uint64_t b = __ballot(win);
+    return rl32(idx, __ffsll((unsigned long long)b) - 1);
 }
 
 // Appends the series ch[0, L) as member n of the run's new population.
@@ -290,7 +359,7 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
         return fa > fb || (fa == fb && a < b);
     };
     for (int32_t i = lane; i < sh.P2; i += kLanes) S.order[i] = (uint16_t)i;
-    __syncthreads();
+    wave_sync();
     for (int32_t k = 2; k <= sh.P2; k <<= 1)
         for (int32_t j = k >> 1; j > 0; j >>= 1) {
             for (int32_t i = lane; i < sh.P2; i += kLanes) {
@@ -304,7 +373,7 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     // the old list (sorted by decreasing fitness) and its column index
     for (int64_t i = lane; i < (int64_t)m * EW; i += kLanes) S.colmask[i] = 0ull;
@@ -316,12 +385,12 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
         S.ealive[e] = 1;
         for (int32_t t = 0; t < le; ++t) S.ecols[e * slot + t] = (uint16_t)R.top_cols[e * slot + t];
     }
-    __syncthreads();
+    wave_sync();
     for (int32_t e = lane; e < n_old; e += kLanes)
         for (int32_t t = 0; t < S.elen[e]; ++t)
             atomicOr((unsigned long long *)&S.colmask[(int64_t)S.ecols[e * slot + t] * EW + e / 64],
                      1ull << (e % 64));
-    __syncthreads();
+    wave_sync();
 
     int32_t n_ent = n_old, settled = 0, old_ptr = 0;
     for (int32_t ii = 0; ii < P; ++ii) {
@@ -331,10 +400,11 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
         for (; old_ptr < n_old && S.efit[old_ptr] >= fx; ++old_ptr) settled += S.ealive[old_ptr];
         if (settled >= K) break;
         const int32_t lx = S.plen[i];
-        const int32_t xc = lane < lx ? (int32_t)S.pcols[i * slot + lane] : -1;
+        const int32_t xc = lane < lx ? (int32_t)S.pcols[i * sh.pstride + lane] : -1;
         // per entry: intersection with x, listed (same series), overlap
         auto entry = [&](int32_t e, bool &listed, bool &over) -> bool {
             int32_t inter = 0;
+#pragma unroll 8
             for (int32_t t = 0; t < lx; ++t) {
                 const int32_t c = rl32(xc, t);
                 inter += (int32_t)((S.colmask[(int64_t)c * EW + e / 64] >> (e % 64)) & 1ull);
@@ -384,7 +454,7 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
             }
             ++settled;
         }
-        __syncthreads();
+        wave_sync();
     }
     // live entries in insertion order, stable by decreasing fitness, first K
     int32_t live = 0;
@@ -401,7 +471,7 @@ __device__ int32_t step5(const StepsArgs &A, const StepsRun &R, const Lds &S, co
             if (rank < K) S.erank[rank] = (uint16_t)e;
         }
     }
-    __syncthreads();
+    wave_sync();
     const int32_t n_top = min(live, K);
     for (int32_t r = lane; r < n_top; r += kLanes) {
         const int32_t e = S.erank[r];
@@ -424,20 +494,20 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
     const LdsShape sh = lds_shape(P, slot, M, A.K);
     const Lds S = lds_map(smem, sh);
     Draws d;
-    d.start(st.rng);
+    d.start(st.rng, (uint32_t)P, (uint32_t)A.wsum, (uint32_t)M);
     bool full = false;
 
     if (A.mode == 0) {
         // Step 1: P distinct random series
         int64_t cur = 0;
         for (int32_t n = 0; n < P;) {
-            const int32_t L = A.len_min + (int32_t)d.below((uint64_t)(A.len_max - A.len_min + 1));
+            const int32_t L = A.len_min + (int32_t)d.below((uint32_t)(A.len_max - A.len_min + 1));
             int32_t ch = -1;
             for (int32_t k = 0; k < L; ++k) {
                 const int32_t c = new_column(d, ch, k, M);
                 if (lane == k) ch = c;
             }
-            if (!tabu_insert(R, ch, L, &full)) {
+            if (!tabu_insert(R, st.arena_used, ch, L, &full)) {
                 if (full) break;
                 continue;
             }
@@ -445,7 +515,6 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
             ++n;
         }
         if (lane == 0) R.off[P] = (int32_t)(R.col_base + cur);
-        st.tabu_used += P;
         st.first_new = 0;
         st.gen = 0;
     } else {
@@ -457,17 +526,17 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
             S.pfit[i] = R.fit[i];
             S.pcnt[i] = R.counts[i];
             const int32_t *src = R.cols + (o - R.col_base);
-            for (int32_t t = 0; t < L; ++t) S.pcols[i * slot + t] = (uint16_t)src[t];
+            for (int32_t t = 0; t < L; ++t) S.pcols[i * sh.pstride + t] = (uint16_t)src[t];
         }
-        __syncthreads();
+        wave_sync();
         // Step 5 with the population of generation st.gen
         st.n_top = step5(A, R, S, sh, st.n_top);
         if (st.gen > 0) st.gens_run = st.gen;
-        __syncthreads();
+        wave_sync();
         if (A.mode == 1) {
             // Step 2: elites and their penalties
             for (int32_t c = lane; c < M; c += kLanes) S.pen[c] = 0u;
-            __syncthreads();
+            wave_sync();
             const int32_t n_e = (int32_t)min<int64_t>(
                 (int64_t)st.n_top, (int64_t)P * A.elite_num / A.elite_den);
             int64_t cur = 0;
@@ -478,13 +547,13 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                 if (lane < L) atomicAdd(&S.pen[ch], 1u);
                 put_member(R, e, cur, ch, L);
             }
-            __syncthreads();
+            wave_sync();
             // Step 3: novel children until the population is full
             const int T = A.tournament;
             int32_t n = n_e, hits = 0;
             while (n < P) {
                 d.need(2 * T + 1);
-                const uint64_t u = d.at(T) % (uint64_t)A.wsum;
+                const uint32_t u = (uint32_t)rl32((int32_t)d.modW, d.used + T);
                 int op = 0;
                 int64_t acc = 0;
                 for (op = 0; op < 5; ++op) {
@@ -494,17 +563,17 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                 const int nsets = op == OP_CROSSOVER ? 2 : 1;
                 int32_t idx;
                 double adj;
-                tournament_lanes(d, nsets, T, P, S, slot, A.powtab, idx, adj);
+                tournament_lanes(d, nsets, T, P, S, sh.pstride, A.powtab, idx, adj);
                 const int32_t ia = tournament_winner(idx, adj, 0, T);
                 const int32_t ib = nsets == 2 ? tournament_winner(idx, adj, T, T) : ia;
                 d.used += nsets * (T + 1) - (nsets == 2 ? 1 : 0);
                 const int32_t la = S.plen[ia];
-                int32_t ch = lane < la ? (int32_t)S.pcols[ia * slot + lane] : -1;
+                int32_t ch = lane < la ? (int32_t)S.pcols[ia * sh.pstride + lane] : -1;
                 int32_t L = la;
                 switch (op) {
                 case OP_INSERT:
                     if (L < A.len_max) {
-                        const int32_t pos = (int32_t)d.below((uint64_t)L + 1);
+                        const int32_t pos = (int32_t)d.below((uint32_t)L + 1);
                         const int32_t c = new_column(d, ch, L, M);
                         const int32_t left = __shfl(ch, max(lane - 1, 0));
                         ch = lane < pos ? ch : (lane == pos ? c : left);
@@ -513,7 +582,7 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                     break;
                 case OP_DELETE:
                     if (L > A.len_min) {
-                        const int32_t pos = (int32_t)d.below((uint64_t)L);
+                        const int32_t pos = (int32_t)d.below((uint32_t)L);
                         const int32_t right = __shfl(ch, min(lane + 1, kLanes - 1));
                         if (lane >= pos) ch = right;
                         --L;
@@ -521,8 +590,8 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                     break;
                 case OP_SWAP:
                     if (L >= 2) {
-                        const int32_t i = (int32_t)d.below((uint64_t)L);
-                        int32_t j = (int32_t)d.below((uint64_t)L - 1);
+                        const int32_t i = (int32_t)d.below((uint32_t)L);
+                        int32_t j = (int32_t)d.below((uint32_t)L - 1);
                         if (j >= i) ++j;
                         const int32_t ci = rl32(ch, i), cj = rl32(ch, j);
                         if (lane == i) ch = cj;
@@ -531,34 +600,34 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                     break;
                 case OP_SUBSTITUTE:
                     if (L < M) {
-                        const int32_t pos = (int32_t)d.below((uint64_t)L);
+                        const int32_t pos = (int32_t)d.below((uint32_t)L);
                         const int32_t c = new_column(d, ch, L, M);
                         if (lane == pos) ch = c;
                     }
                     break;
                 default: {   // one-point crossover of Fig. 1e
                     const int32_t lb = S.plen[ib];
-                    const int32_t b = lane < lb ? (int32_t)S.pcols[ib * slot + lane] : -1;
-                    const int32_t i = 1 + (int32_t)d.below((uint64_t)la);
-                    const int32_t j = (int32_t)d.below((uint64_t)lb);
+                    const int32_t b = lane < lb ? (int32_t)S.pcols[ib * sh.pstride + lane] : -1;
+                    const int32_t i = 1 + (int32_t)d.below((uint32_t)la);
+                    const int32_t j = (int32_t)d.below((uint32_t)lb);
                     const bool keep = lane >= j && lane < lb && !series_has(ch, i, b);
                     const uint64_t km = __ballot(keep);
                     const int32_t rank = __popcll(km & ((1ull << lane) - 1ull));
                     const int32_t n_c = min(i + __popcll(km), A.len_max);
                     S.cbuf[lane] = lane < i ? ch : -1;
-                    __syncthreads();
+                    wave_sync();
                     if (keep && i + rank < A.len_max) S.cbuf[i + rank] = b;
-                    __syncthreads();
+                    wave_sync();
                     if (n_c >= A.len_min) {
                         ch = S.cbuf[lane];
                         L = n_c;
                     }
-                    __syncthreads();
+                    wave_sync();
                     break;
                 }
                 }
                 if (lane >= L) ch = -1;
-                if (!tabu_insert(R, ch, L, &full)) {
+                if (!tabu_insert(R, st.arena_used, ch, L, &full)) {
                     if (full) break;
                     if (++hits > A.tabu_limit) {
                         st.stopped = 1;
@@ -566,11 +635,10 @@ __global__ __launch_bounds__(kLanes) void evolve_steps_kernel(StepsArgs A) {
                     }
                     continue;
                 }
-                ++st.tabu_used;
                 if (lane < L) atomicAdd(&S.pen[ch], 1u);
                 put_member(R, n, cur, ch, L);
                 ++n;
-                __syncthreads();
+                wave_sync();
             }
             // a stopped run leaves empty members behind (never read)
             for (int32_t i = n + lane; i <= P; i += kLanes) R.off[i] = (int32_t)(R.col_base + cur);
@@ -590,7 +658,6 @@ int64_t steps_lds_bytes(int32_t P, int32_t slot, int32_t m, int32_t K) {
 }
 
 hipError_t launch_steps(const StepsArgs &a, hipStream_t stream) {
-    static_assert(kMaxSlotCols >= 58, "slot columns");
     // (dynamic LDS above 64 KiB; a runtime without the attribute fails the
     // launch itself if the size is not allowed)
     if (hipFuncSetAttribute((const void *)evolve_steps_kernel,
