@@ -25,7 +25,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 SOURCES = ["ebic_kernels.hip", "ebic_batch_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
            "ebic_mlp_kernels.hip", "ebic_mlp.cpp", "ebic_surrogate.cpp", "ebic_scores.hip",
-           "ebic_checkpoint.cpp", "ebic_noalloc.hip", "ebic_steps.hip"]
+           "ebic_checkpoint.cpp", "ebic_noalloc.hip", "ebic_steps.hip",
+           "ebic_mlp_fused.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
           "-I", INCLUDE, "-I", CSRC]

@@ -38,6 +38,14 @@ struct ebic_mlp {
     uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
     float *ws = nullptr;
     int64_t cap_ws = 0;
+    // fused step (embed_dim 32, hidden 256): transposed BF16 weights and
+    // per-step buffers for up to cap_Bp (padded) candidates
+    bool fused = false;
+    uint16_t *W1bT = nullptr, *W2bT = nullptr;
+    int64_t cap_Bp = 0;
+    uint16_t *XrT = nullptr, *H1rT = nullptr, *dZ2rT = nullptr, *dZ1rT = nullptr;
+    float *fdX = nullptr, *ws1 = nullptr, *ws2 = nullptr, *pw3 = nullptr, *pb2 = nullptr,
+          *pb1 = nullptr, *pb3 = nullptr;
 };
 
 namespace {
@@ -110,6 +118,138 @@ ebic_status reserve(ebic_mlp *m, int64_t B, int64_t L) {
 
 int32_t splits_for(int32_t B) { return std::max(1, std::min(kMaxSplits, B / 256)); }
 
+int64_t padded_batch(int64_t B) {
+    const int64_t c = mlp::fused_chunk();
+    return (B + c - 1) / c * c;
+}
+
+// Buffers of the fused step for a batch of B candidates.
+ebic_status reserve_fused(ebic_mlp *m, int64_t B) {
+    const int64_t Bp = padded_batch(B);
+    if (Bp <= m->cap_Bp) return EBIC_OK;
+    MHIP(hipStreamSynchronize(m->stream));
+    const int64_t c = std::max<int64_t>(Bp, m->cap_Bp * 2);
+    const int64_t H = m->H, D2 = 2 * m->D;
+    const int64_t tiles = c / mlp::fused_tile_rows(), nS = c / mlp::fused_chunk();
+    MHIP(dalloc(m->XrT, D2 * c));
+    MHIP(dalloc(m->H1rT, H * c));
+    MHIP(dalloc(m->dZ2rT, H * c));
+    MHIP(dalloc(m->dZ1rT, H * c));
+    MHIP(dalloc(m->fdX, c * D2));
+    MHIP(dalloc(m->ws1, nS * H * D2));
+    MHIP(dalloc(m->ws2, nS * H * H));
+    MHIP(dalloc(m->pw3, tiles * H));
+    MHIP(dalloc(m->pb2, tiles * H));
+    MHIP(dalloc(m->pb1, tiles * H));
+    MHIP(dalloc(m->pb3, tiles));
+    m->cap_Bp = c;
+    return EBIC_OK;
+}
+
+mlp::FusedRows fused_rows_args(ebic_mlp *m, int32_t B, bool train) {
+    mlp::FusedRows a{};
+    a.E = m->p + m->oE;
+    a.F = m->p + m->oF;
+    a.T = m->p + m->oT;
+    a.Zl = m->p + m->oZ;
+    a.off = m->off;
+    a.cols = m->cols;
+    a.B = B;
+    a.Bp = padded_batch(B);
+    a.W1b = m->W1b;
+    a.W1bT = m->W1bT;
+    a.W2b = m->W2b;
+    a.W2bT = m->W2bT;
+    a.w3b = m->w3b;
+    a.b1 = m->p + m->ob1;
+    a.b2 = m->p + m->ob2;
+    a.b3 = m->p + m->ob3;
+    a.target = train ? m->t : nullptr;
+    a.y = m->y;
+    a.sq = m->sq;
+    a.XrT = m->XrT;
+    a.H1rT = m->H1rT;
+    a.dZ2rT = m->dZ2rT;
+    a.dZ1rT = m->dZ1rT;
+    a.dX = m->fdX;
+    a.pw3 = m->pw3;
+    a.pb2 = m->pb2;
+    a.pb1 = m->pb1;
+    a.pb3 = m->pb3;
+    return a;
+}
+
+// One fused step: rows, gradients, then the update in `mode`
+// (mlp::kUpdateGradients leaves the gradient in m->g; mlp::kUpdateAdam
+// also applies Adam with bias corrections c1, c2).
+ebic_status fused_step(ebic_mlp *m, int32_t B, int32_t mode, float c1, float c2) {
+    const int64_t Bp = padded_batch(B);
+    hipStream_t s = m->stream;
+    MHIP(mlp::fused_rows(fused_rows_args(m, B, true), s));
+    mlp::FusedGrads g{};
+    g.Bp = Bp;
+    g.M = m->M;
+    g.XrT = m->XrT;
+    g.H1rT = m->H1rT;
+    g.dZ2rT = m->dZ2rT;
+    g.dZ1rT = m->dZ1rT;
+    g.dX = m->fdX;
+    g.F = m->p + m->oF;
+    g.T = m->p + m->oT;
+    g.off = m->off;
+    g.cols = m->cols;
+    g.occ_start = m->occ_start;
+    g.occ_pos = m->occ_pos;
+    g.occ_b = m->occ_b;
+    g.len_start = m->len_start;
+    g.len_b = m->len_b;
+    g.ws1 = m->ws1;
+    g.ws2 = m->ws2;
+    g.pw3 = m->pw3;
+    g.pb2 = m->pb2;
+    g.pb1 = m->pb1;
+    g.pb3 = m->pb3;
+    g.gE = m->g + m->oE;
+    g.gF = m->g + m->oF;
+    g.gT = m->g + m->oT;
+    g.gZ = m->g + m->oZ;
+    g.gb1 = m->g + m->ob1;
+    g.gb2 = m->g + m->ob2;
+    g.gw3 = m->g + m->ow3;
+    g.gb3 = m->g + m->ob3;
+    MHIP(mlp::fused_grads(g, s));
+    mlp::FusedUpdate u{};
+    u.mode = mode;
+    u.n_params = m->n_params;
+    u.oW1 = m->oW1;
+    u.ob1 = m->ob1;
+    u.oW2 = m->oW2;
+    u.ob2 = m->ob2;
+    u.ow3 = m->ow3;
+    u.ob3 = m->ob3;
+    u.nS = Bp / mlp::fused_chunk();
+    u.nTiles = Bp / mlp::fused_tile_rows();
+    u.p = m->p;
+    u.g = m->g;
+    u.m1 = m->m1;
+    u.m2 = m->m2;
+    u.ws1 = m->ws1;
+    u.ws2 = m->ws2;
+    u.lr = m->cfg.lr;
+    u.beta1 = m->cfg.beta1;
+    u.beta2 = m->cfg.beta2;
+    u.eps = m->cfg.eps;
+    u.c1 = c1;
+    u.c2 = c2;
+    u.W1b = m->W1b;
+    u.W1bT = m->W1bT;
+    u.W2b = m->W2b;
+    u.W2bT = m->W2bT;
+    u.w3b = m->w3b;
+    MHIP(mlp::fused_update(u, s));
+    return EBIC_OK;
+}
+
 bool check_cbf(const ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t B) {
     if (off[0] != 0) return false;
     for (int32_t b = 0; b < B; ++b) {
@@ -171,6 +311,12 @@ ebic_status upload(ebic_mlp *m, const int32_t *off, const int32_t *cols, int32_t
 ebic_status forward(ebic_mlp *m, int32_t B) {
     const int32_t D = m->D, H = m->H;
     hipStream_t s = m->stream;
+    if (m->fused) {
+        ebic_status st = reserve_fused(m, B);
+        if (st != EBIC_OK) return st;
+        MHIP(mlp::fused_rows(fused_rows_args(m, B, false), s));
+        return EBIC_OK;
+    }
     const int32_t D2 = 2 * D;
     MHIP(mlp::pool_fwd(m->p + m->oE, m->p + m->oF, m->p + m->oT, m->p + m->oZ, D, m->off,
                        m->cols, B, m->X, m->Xb, s));
@@ -213,6 +359,25 @@ ebic_status backward(ebic_mlp *m, int32_t B) {
 }
 
 ebic_status refresh_bf16(ebic_mlp *m) {
+    if (m->fused) {
+        mlp::FusedUpdate u{};
+        u.mode = mlp::kUpdateCast;
+        u.n_params = m->n_params;
+        u.oW1 = m->oW1;
+        u.ob1 = m->ob1;
+        u.oW2 = m->oW2;
+        u.ob2 = m->ob2;
+        u.ow3 = m->ow3;
+        u.ob3 = m->ob3;
+        u.p = m->p;
+        u.W1b = m->W1b;
+        u.W1bT = m->W1bT;
+        u.W2b = m->W2b;
+        u.W2bT = m->W2bT;
+        u.w3b = m->w3b;
+        MHIP(mlp::fused_update(u, m->stream));
+        return EBIC_OK;
+    }
     MHIP(mlp::cast_bf16(m->p + m->oW1, (int64_t)m->H * 2 * m->D, m->W1b, m->stream));
     MHIP(mlp::cast_bf16(m->p + m->oW2, (int64_t)m->H * m->H, m->W2b, m->stream));
     MHIP(mlp::cast_bf16(m->p + m->ow3, (int64_t)m->H, m->w3b, m->stream));
@@ -301,6 +466,9 @@ ebic_status ebic_mlp_create(int32_t n_cols, const ebic_mlp_config *cfg, uint64_t
     if (e == hipSuccess) e = dalloc(m->W1b, H * 2 * D);
     if (e == hipSuccess) e = dalloc(m->W2b, H * H);
     if (e == hipSuccess) e = dalloc(m->w3b, H);
+    m->fused = mlp::fused_shape(m->D, m->H);
+    if (m->fused && e == hipSuccess) e = dalloc(m->W1bT, H * 2 * D);
+    if (m->fused && e == hipSuccess) e = dalloc(m->W2bT, H * H);
     if (e != hipSuccess) return fail(e, "model buffers");
     ebic_status st = ebic_mlp_set_params(m.get(), init.data());
     if (st != EBIC_OK) {
@@ -317,7 +485,9 @@ ebic_status ebic_mlp_destroy(ebic_mlp *m) {
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     void *bufs[] = {m->p, m->g, m->m1, m->m2, m->W1b, m->W2b, m->w3b, m->off, m->cols,
                     m->occ_start, m->occ_pos, m->occ_b, m->len_start, m->len_b, m->X, m->Z1, m->Z2, m->y, m->t, m->dy, m->sq,
-                    m->dZ2, m->G1, m->dZ1, m->dX, m->Xb, m->H1b, m->H2b, m->dZ2b, m->dZ1b, m->ws};
+                    m->dZ2, m->G1, m->dZ1, m->dX, m->Xb, m->H1b, m->H2b, m->dZ2b, m->dZ1b, m->ws,
+                    m->W1bT, m->W2bT, m->XrT, m->H1rT, m->dZ2rT, m->dZ1rT, m->fdX, m->ws1,
+                    m->ws2, m->pw3, m->pb2, m->pb1, m->pb3};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (m->stream) (void)hipStreamDestroy(m->stream);
@@ -367,7 +537,13 @@ ebic_status ebic_mlp_gradients(ebic_mlp *m, const int32_t *offsets, const int32_
     MHIP(hipSetDevice(m->device));
     ebic_status st = upload(m, offsets, cols, B, target, true);
     if (st != EBIC_OK) return st;
-    if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
+    if (m->fused) {
+        if ((st = reserve_fused(m, B)) != EBIC_OK ||
+            (st = fused_step(m, B, mlp::kUpdateGradients, 1.f, 1.f)) != EBIC_OK)
+            return st;
+    } else if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) {
+        return st;
+    }
     MHIP(hipMemcpyAsync(grad, m->g, sizeof(float) * (size_t)m->n_params, hipMemcpyDeviceToHost,
                         m->stream));
     const float l = host_loss(m, B, &st);
@@ -383,7 +559,15 @@ ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *c
     MHIP(hipSetDevice(m->device));
     ebic_status st = upload(m, offsets, cols, B, target, true);
     if (st != EBIC_OK) return st;
+    if (m->fused && (st = reserve_fused(m, B)) != EBIC_OK) return st;
     for (int32_t k = 0; k < steps; ++k) {
+        if (m->fused) {
+            m->step += 1;
+            const float c1 = 1.f - std::pow(m->cfg.beta1, (float)m->step);
+            const float c2 = 1.f - std::pow(m->cfg.beta2, (float)m->step);
+            if ((st = fused_step(m, B, mlp::kUpdateAdam, c1, c2)) != EBIC_OK) return st;
+            continue;
+        }
         if ((st = forward(m, B)) != EBIC_OK || (st = backward(m, B)) != EBIC_OK) return st;
         m->step += 1;
         const float c1 = 1.f - std::pow(m->cfg.beta1, (float)m->step);

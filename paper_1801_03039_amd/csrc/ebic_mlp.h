@@ -52,5 +52,52 @@ hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, float
                 float beta2, float eps, float c1, float c2, hipStream_t s);
 hipError_t cast_bf16(const float *src, int64_t n, uint16_t *dst, hipStream_t s);
 
+// ------------------------------------------------ fused step (D 32, H 256) --
+// (ebic_mlp_fused.hip) Three launches per training step: rows (forward and
+// per-candidate backward per tile of candidates), grads (weight and
+// embedding gradients), update (gradient sums, Adam, BF16 copies).
+bool fused_shape(int32_t D, int32_t H);
+int32_t fused_tile_rows();   // candidates per rows workgroup
+int32_t fused_chunk();       // candidates per weight-gradient partial; Bp is a multiple
+
+struct FusedRows {
+    const float *E, *F, *T, *Zl;
+    const int32_t *off, *cols;
+    int64_t B, Bp;                   // candidates, padded to a multiple of fused_chunk()
+    const uint16_t *W1b, *W1bT, *W2b, *W2bT, *w3b;
+    const float *b1, *b2, *b3;
+    const float *target;             // nullptr: forward only (y)
+    float *y, *sq;
+    uint16_t *XrT, *H1rT, *dZ2rT, *dZ1rT;   // feature-major [features][Bp]
+    float *dX;                       // [Bp][2D]
+    float *pw3, *pb2, *pb1, *pb3;    // per row tile: [tiles][H] (pb3: [tiles])
+};
+
+struct FusedGrads {
+    int64_t Bp;
+    int32_t M;
+    const uint16_t *XrT, *H1rT, *dZ2rT, *dZ1rT;
+    const float *dX, *F, *T;
+    const int32_t *off, *cols, *occ_start, *occ_pos, *occ_b, *len_start, *len_b;
+    float *ws1, *ws2;                // [Bp / chunk][H][2D], [Bp / chunk][H][H]
+    const float *pw3, *pb2, *pb1, *pb3;   // the rows kernel's per-tile sums
+    float *gE, *gF, *gT, *gZ, *gb1, *gb2, *gw3, *gb3;
+};
+
+enum { kUpdateCast = 0, kUpdateGradients = 1, kUpdateAdam = 2 };
+struct FusedUpdate {
+    int32_t mode;
+    int64_t n_params, oW1, ob1, oW2, ob2, ow3, ob3;
+    int64_t nS, nTiles;
+    float *p, *g, *m1, *m2;
+    const float *ws1, *ws2;
+    float lr, beta1, beta2, eps, c1, c2;
+    uint16_t *W1b, *W1bT, *W2b, *W2bT, *w3b;
+};
+
+hipError_t fused_rows(const FusedRows &a, hipStream_t s);
+hipError_t fused_grads(const FusedGrads &g, hipStream_t s);
+hipError_t fused_update(const FusedUpdate &u, hipStream_t s);
+
 }  // namespace mlp
 }  // namespace ebic
