@@ -100,12 +100,14 @@ __device__ __forceinline__ void finish_part(int64_t c, uint32_t cnt, bool bad, i
 // lane reads lt(p,q) -- and lt(q,p) for the falling direction -- from the
 // pairwise order index and folds the violation words (complements) into K+1
 // saturating bit-sliced counters per direction: c[i] has bit b set when row
-// b has more than i violations.  lt(q,p) is read only for pairs whose tie
-// flag is set; otherwise it is ~lt(p,q) (lt(p,p) itself for a repeated
-// column).  Loads for kUnroll pairs are issued before
-// any is consumed (the lane's latency chain is one order-word round trip per
-// kUnroll pairs), and a lane stops once every row of its word is rejected in
-// every enabled direction.
+// b has more than i violations.  lt(q,p) is read only for pairs that may
+// tie (a set tie flag, or a set bit of the tie-pair bitmap); otherwise it is
+// ~lt(p,q) (lt(p,p) itself for a repeated column).  Single-run workgroups
+// look every staged pair up in the bitmap while staging, and run a loop
+// without any tie test when none is set.  Loads for kUnroll pairs are issued
+// before any is consumed (the lane's latency chain is one order-word round
+// trip per kUnroll pairs), and a lane stops once every row of its word is
+// rejected in every enabled direction.
 constexpr int kIdxLds = 4096;   // staged column entries per workgroup
 constexpr int kUnroll = 4;   // pairs per batch of loads (single-run default)
 constexpr int kWordsPerLane = 2;   // 64-row words per lane (flattened single-run tiling)
@@ -125,13 +127,21 @@ __device__ __forceinline__ void fold(uint64_t (&cu)[K + 1], uint64_t (&cd)[K + 1
     }
 }
 
-// LDS of one tile: the staged CBF columns and, for whole-candidate tiles,
-// the per-candidate row counts and malformed flags.
+// LDS of one tile: the staged CBF columns, for whole-candidate tiles the
+// per-candidate row counts and malformed flags, and the tie-pair bitmap.
 struct TileLds {
     int32_t cols[kIdxLds];
     int32_t rows[kBlock];
     int32_t bad[kBlock];
+    uint32_t tbits[kTieWords];
+    int32_t any_tied;        // a staged consecutive pair is in the tie-pair bitmap
 };
+
+// How the falling test learns that a pair has a tied row (lt(q,p) is then
+// read from the index instead of taken as ~lt(p,q)): never (the matrix has
+// no tied pair), from the m*m byte flags (one load per pair), or from the
+// tie-pair bitmap staged in LDS.
+enum TieMode { kTieNone = 0, kTieFlags = 1, kTieBitmap = 2 };
 
 // V consecutive order words of one pair, read with 16-byte loads when V > 1
 // (the caller keeps the address 16-byte aligned).
@@ -181,7 +191,7 @@ struct ShortBatch<0> {
 //     kAlignedThreads lanes); counts are summed with LDS atomics and the
 //     first lane of each candidate writes its result after a workgroup
 //     barrier -- no global atomics and no accumulator scratch.
-template <int K, bool NEG, int U, int V, bool ALIGNED, bool TIES = true, bool OFF32 = false,
+template <int K, bool NEG, int U, int V, bool ALIGNED, int TIES = kTieFlags, bool OFF32 = false,
           bool TAIL = false>
 __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uint32_t cpw,
                                            const int32_t *__restrict__ offsets,
@@ -222,6 +232,16 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
     const int64_t w0 = (int64_t)g * V;                           // first word of the item
     const int64_t c = R.cand_base + cl;                          // candidate in the launch
 
+    // the tie-pair bitmap, ordered before its first use by the barrier below
+    if constexpr (NEG && TIES == kTieBitmap) {
+        const auto tb = as_global(R.tbits);
+        for (int i = tid; i < kTieWords; i += (int)blockDim.x) lds.tbits[i] = tb[i];
+    }
+    auto in_bitmap = [&](int64_t pq) -> bool {
+        const uint32_t h = tie_hash((uint32_t)pq);
+        return ((lds.tbits[h >> 5] >> (h & 31)) & 1u) != 0;
+    };
+
     const int64_t start = offsets[c], end = offsets[c + 1];
     const bool ok_range = start >= 0 && end <= n_entries && end > start;
     const int32_t L = ok_range ? (int32_t)(end - start) : 0;
@@ -237,20 +257,34 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
         s_rows[tid] = 0;
         s_bad[tid] = 0;
     }
+    if (tid == 0) lds.any_tied = 0;
     const bool span_ok = b0 >= 0 && b1 <= n_entries && b1 >= b0 && b1 - b0 <= kIdxLds;
     const bool lane_ok = !ok_range || (start >= b0 && end <= b1);
     const bool use_lds = __syncthreads_and(span_ok && lane_ok) != 0;
     // Staging also checks every staged column: when none is out of range
-    // (the common case) the per-candidate validation below is skipped.
+    // (the common case) the per-candidate validation below is skipped.  With
+    // the tie-pair bitmap it also looks up every staged consecutive pair
+    // (pairs that straddle two candidates included): a workgroup none of
+    // whose pairs is in the bitmap runs the tie-free loop.
     bool staged_bad = true;
+    [[maybe_unused]] bool staged_tie = true;
     if (use_lds) {
-        bool inval = false;
+        bool inval = false, any_tied = false;
         for (int32_t e = tid; e < (int32_t)(b1 - b0); e += (int32_t)blockDim.x) {
             const int32_t x = cols[b0 + e];
             inval |= x < 0 || x >= m;
             s_cols[e] = x;
+            if constexpr (NEG && TIES == kTieBitmap) {
+                if (e > 0) {
+                    const int32_t xp = cols[b0 + e - 1];
+                    if (x >= 0 && x < m && xp >= 0 && xp < m && x != xp)
+                        any_tied |= in_bitmap((int64_t)xp * m + x);
+                }
+            }
         }
+        if (any_tied) lds.any_tied = 1;
         staged_bad = __syncthreads_or(inval) != 0;
+        staged_tie = lds.any_tied != 0;
     }
     const int32_t lds0 = (int32_t)(start - b0);
 
@@ -268,9 +302,17 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
         for (int i = 0; i <= K; ++i) cu[v][i] = cd[v][i] = 0ull;
     bool bad = false;
 
-    // Per-lane work, instantiated for columns in LDS or in global memory.
-    auto lane_work = [&](auto from_lds) {
+    // Per-lane work, instantiated for columns in LDS or in global memory and
+    // for a tie mode (TIES, or kTieNone for a workgroup without tied pairs).
+    auto lane_work = [&](auto from_lds, auto tie_mode, auto unroll) {
         constexpr bool kLds = decltype(from_lds)::value;
+        constexpr int TM = decltype(tie_mode)::value;
+        constexpr int UU = decltype(unroll)::value;
+        auto tied = [&](int64_t pq) -> uint8_t {
+            if constexpr (TM == kTieFlags) return tie[pq];
+            if constexpr (TM == kTieBitmap) return in_bitmap(pq) ? 1 : 0;
+            return 0;
+        };
         auto col = [&](int32_t t) -> int32_t {
             if constexpr (kLds) return s_cols[lds0 + t];
             else return cols[start + t];
@@ -281,12 +323,12 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
         // clamp column indices so that no read leaves the index.
         if (active && g == 0) bad = !ok_range;
         if (active && g == 0 && (!kLds || staged_bad)) {
-            for (int32_t t = 0; t < L; t += U) {
-                int32_t x[U];
+            for (int32_t t = 0; t < L; t += UU) {
+                int32_t x[UU];
 #pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = col(min(t + u, L - 1));
+                for (int u = 0; u < UU; ++u) x[u] = col(min(t + u, L - 1));
 #pragma unroll
-                for (int u = 0; u < U; ++u) bad |= (x[u] < 0 || x[u] >= m);
+                for (int u = 0; u < UU; ++u) bad |= (x[u] < 0 || x[u] >= m);
             }
         }
         if (!any_valid) return;
@@ -324,7 +366,7 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                 for (int u = 0; u < N; ++u) {
                     const int64_t pq = (int64_t)pp * m + q[u];
                     load_words<V>(words_at(pq), lu[u]);
-                    if (NEG) tf[u] = TIES ? tie[pq] : 0;
+                    if (NEG) tf[u] = tied(pq);
                     pp = q[u];
                 }
                 if (NEG) {
@@ -332,11 +374,12 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                     pp = p;
 #pragma unroll
                     for (int u = 0; u < N; ++u) {
-                        if (TIES && tf[u]) {
+                        if (TM != kTieNone && tf[u]) {
                             load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
                         } else {
                             // a repeated column is its own reverse: lt(p,p) = 0
-                            const bool self = !TIES && q[u] == pp;
+                            // (the byte flags mark it as tied instead)
+                            const bool self = TM != kTieFlags && q[u] == pp;
 #pragma unroll
                             for (int v = 0; v < V; ++v) ld[u][v] = self ? lu[u][v] : ~lu[u][v];
                         }
@@ -355,40 +398,45 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                     live |= valid[v] & ~(NEG ? (cu[v][K] & cd[v][K]) : cu[v][K]);
                 return live != 0ull;
             };
-            // Whole batches of U pairs, then the last L - t < U pairs as one
+            // Whole batches of UU pairs, then the last L - t < UU pairs as one
             // shorter batch: no load reads past the end of the series.
             int32_t t = 1;
             bool undecided = true;
-            for (; t + U <= L; t += U)
-                if (!(undecided = batch(std::integral_constant<int, U>{}, t))) break;
+            for (; t + UU <= L; t += UU)
+                if (!(undecided = batch(std::integral_constant<int, UU>{}, t))) break;
             if (undecided)
-                ShortBatch<U - 1>::run(L - t, [&](auto n) { (void)batch(n, t); });
+                ShortBatch<UU - 1>::run(L - t, [&](auto n) { (void)batch(n, t); });
         } else {
             const int32_t last = L - 1;
             int32_t p = col(0);
             p = (p < 0 || p >= m) ? 0 : p;
-            for (int32_t t = 1; t < L; t += U) {
+            for (int32_t t = 1; t < L; t += UU) {
                 // Column reads and order-word loads of the batch are issued
-                // unconditionally (indices past the end repeat the last column,
-                // a harmless in-bounds read whose words are then ignored).
-                int32_t q[U];
+                // unconditionally (slots past the end repeat the last pair, a
+                // harmless in-bounds read whose words are then ignored).
+                int32_t q[UU];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < UU; ++u) {
                     const int32_t x = col(min(t + u, last));
                     q[u] = (x < 0 || x >= m) ? 0 : x;
                 }
-                uint64_t lu[U][V], ld[U][V];
-                uint8_t tf[U];
+                uint64_t lu[UU][V], ld[UU][V];
+                uint8_t tf[UU];
                 int32_t pp = p;
+                int64_t pq_prev = 0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t pq = (int64_t)pp * m + q[u];
+                for (int u = 0; u < UU; ++u) {
+                    // a slot past the end re-reads the words of the last
+                    // pair (just fetched) rather than a diagonal row
+                    int64_t pq = (int64_t)pp * m + q[u];
+                    if (u > 0) pq = t + u < L ? pq : pq_prev;
+                    pq_prev = pq;
                     load_words<V>(words_at(pq), lu[u]);
-                    if (NEG) tf[u] = TIES ? tie[pq] : 0;
+                    if (NEG) tf[u] = tied(pq);
                     pp = q[u];
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < UU; ++u) {
                     const bool in = t + u < L;
 #pragma unroll
                     for (int v = 0; v < V; ++v) lu[u][v] = in ? lu[u][v] : ~0ull;
@@ -399,12 +447,13 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                     // slots past the end of the series break nothing.
                     pp = p;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (TIES && tf[u]) {
+                    for (int u = 0; u < UU; ++u) {
+                        if (TM != kTieNone && tf[u]) {
                             load_words<V>(words_at((int64_t)q[u] * m + pp), ld[u]);
                         } else {
                             // a repeated column is its own reverse: lt(p,p) = 0
-                            const bool self = !TIES && q[u] == pp;
+                            // (the byte flags mark it as tied instead)
+                            const bool self = TM != kTieFlags && q[u] == pp;
 #pragma unroll
                             for (int v = 0; v < V; ++v) ld[u][v] = self ? lu[u][v] : ~lu[u][v];
                         }
@@ -414,7 +463,7 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < UU; ++u)
 #pragma unroll
                     for (int v = 0; v < V; ++v)
                         fold<K, NEG>(cu[v], cd[v], lu[u][v], NEG ? ld[u][v] : 0ull);
@@ -427,10 +476,26 @@ __device__ __forceinline__ void index_tile(const IndexRun &R, uint32_t tile, uin
             }
         }
     };
-    if (use_lds)
-        lane_work(std::true_type{});
-    else
-        lane_work(std::false_type{});
+    using tie_none = std::integral_constant<int, kTieNone>;
+    using tie_mode = std::integral_constant<int, TIES>;
+    using unroll = std::integral_constant<int, U>;
+    if constexpr (NEG && TIES == kTieBitmap) {
+        // Workgroups with a tied pair (rare) take batches of at most 2
+        // pairs: the reverse words then never hold the kernel's register
+        // count above that of the tie-free loop.
+        using unroll_tied = std::integral_constant<int, (U < 2 ? U : 2)>;
+        if (use_lds && !staged_bad && !staged_tie)
+            lane_work(std::true_type{}, tie_none{}, unroll{});
+        else if (use_lds)
+            lane_work(std::true_type{}, tie_mode{}, unroll_tied{});
+        else
+            lane_work(std::false_type{}, tie_mode{}, unroll_tied{});
+    } else {
+        if (use_lds)
+            lane_work(std::true_type{}, tie_mode{}, unroll{});
+        else
+            lane_work(std::false_type{}, tie_mode{}, unroll{});
+    }
 
     int32_t rows = 0;
 #pragma unroll

@@ -29,11 +29,23 @@ struct DeviceBuf {
 hipError_t launch_ingest(const float *src, int64_t n, int32_t m, int64_t ld, int32_t layout,
                          int64_t npad, float *dst, hipStream_t stream);
 
-// Builds the pairwise order index, its per-pair tie flags (m*m bytes) and
-// any_tie[0] = whether two distinct columns tie on some row.
+// Tie-pair filter of the falling test: a bitmap of kTieBits bits in which
+// ordered pair id p*m + q (p != q) sets bit tie_hash(p*m + q) when columns
+// p and q have a tied or unordered row.  Every tied pair sets its bit, so a
+// clear bit proves lt(q,p) = ~lt(p,q) on the valid rows; a set bit of an
+// untied pair (a hash collision) only costs a read of the true reverse word.
+constexpr int kTieBitsLog2 = 13;
+constexpr int kTieWords = (1 << kTieBitsLog2) / 32;   // 1 KiB
+__host__ __device__ inline uint32_t tie_hash(uint32_t pq) {
+    return (pq * 0x9E3779B1u) >> (32 - kTieBitsLog2);   // Fibonacci hashing
+}
+
+// Builds the pairwise order index, its per-pair tie flags (m*m bytes), the
+// tie-pair bitmap (kTieWords words) and any_tie[0] = whether two distinct
+// columns tie on some row.
 hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               int64_t wpad, uint64_t *idx, uint8_t *tie, int32_t *any_tie,
-                              hipStream_t stream);
+                              uint32_t *tbits, hipStream_t stream);
 
 struct EvalArgs {
     const int32_t *offsets;
@@ -62,6 +74,7 @@ struct IndexRun {
     int64_t mask_base;       // first mask word of the run (when masks are written)
     int32_t cpw;             // batched tiles: whole candidates per tile (0: flattened tiles)
     int32_t reserved;
+    const uint32_t *tbits;   // tie-pair bitmap (single-run launches; batched runs read `tie`)
 };
 
 // Batched launch shapes: unroll x words per lane is at most this.
@@ -171,10 +184,10 @@ bool pack_valid_cbf(ebic_ctx *ctx, const int32_t *offsets, const int32_t *cols, 
 hipError_t launch_eval_direct(const float *a, int64_t n, int64_t npad, int32_t m, int64_t W,
                               const EvalArgs &e, hipStream_t stream);
 
-// `ties`: some column pair of the matrix has a tied or unordered row (any
-// tie flag set); when false the falling test never reads flags or reverse
+// `ties`: two distinct columns of the matrix have a tied or unordered row;
+// when false the falling test never reads the tie-pair bitmap or reverse
 // words.
-hipError_t launch_eval_index(const uint64_t *idx, const uint8_t *tie, bool ties, int64_t n,
+hipError_t launch_eval_index(const uint64_t *idx, const uint32_t *tbits, bool ties, int64_t n,
                              int32_t m, int64_t W, int64_t wpad, const EvalArgs &e,
                              hipStream_t stream);
 
@@ -189,7 +202,9 @@ struct ebic_ctx {
     double *d_log = nullptr;     // ln(i), i = 0..n
     // pairwise order index
     uint64_t *d_idx = nullptr;
-    uint8_t *d_tie = nullptr;    // m*m tie flags of the index, then an int32 any-tie flag
+    // m*m tie flags of the index, an int32 any-tie flag, then the tie-pair
+    // bitmap (tie_bits_offset)
+    uint8_t *d_tie = nullptr;
     bool any_tie = true;         // two distinct columns tie (known once the index is built)
     int64_t idx_bytes = 0;
     int64_t idx_budget = 0;

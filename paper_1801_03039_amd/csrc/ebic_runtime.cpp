@@ -92,8 +92,10 @@ ebic_status ensure_scratch(ebic_ctx *ctx, int64_t P) {
     return grow(ctx, ctx->d_acc, ctx->cap_P, P, true);
 }
 
-// The any-tie flag follows the m*m tie flags, 8-byte aligned.
+// The any-tie flag follows the m*m tie flags, 8-byte aligned; the tie-pair
+// bitmap follows it, 16-byte aligned.
 size_t tie_flag_offset(int32_t m) { return ((size_t)m * (size_t)m + 7) / 8 * 8; }
+size_t tie_bits_offset(int32_t m) { return tie_flag_offset(m) + 16; }
 
 int64_t index_bytes_for(int32_t m, int64_t wpad) {
     return (int64_t)m * (int64_t)m * (wpad * 8 + 1);  // order words + tie flags
@@ -111,7 +113,7 @@ ebic_status build_index(ebic_ctx *ctx) {
                                                std::to_string(ctx->idx_bytes) + " bytes)");
         }
         ctx->d_idx = static_cast<uint64_t *>(p);
-        e = hipMalloc(&p, tie_flag_offset(ctx->m) + sizeof(int32_t));
+        e = hipMalloc(&p, tie_bits_offset(ctx->m) + kTieWords * sizeof(uint32_t));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(ctx->d_idx);
@@ -125,8 +127,9 @@ ebic_status build_index(ebic_ctx *ctx) {
     HIP_TRY(ctx, hipEventCreate(&e1));
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
     int32_t *d_any = reinterpret_cast<int32_t *>(ctx->d_tie + tie_flag_offset(ctx->m));
+    uint32_t *d_bits = reinterpret_cast<uint32_t *>(ctx->d_tie + tie_bits_offset(ctx->m));
     HIP_TRY(ctx, launch_index_build(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, ctx->wpad,
-                                    ctx->d_idx, ctx->d_tie, d_any, ctx->stream));
+                                    ctx->d_idx, ctx->d_tie, d_any, d_bits, ctx->stream));
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(e1));
     float ms = 0.f;
@@ -174,8 +177,10 @@ ebic_status launch_all(ebic_ctx *ctx, const EvalArgs &e, bool use_index, hipStre
     if (items > kMaxLaunchThreads)
         return fail(ctx, EBIC_E_ARG, "population too large for one launch; split it");
     if (use_index)
-        HIP_TRY(ctx, launch_eval_index(ctx->d_idx, ctx->d_tie, ctx->any_tie, ctx->n, ctx->m,
-                                       ctx->W, ctx->wpad, e, s));
+        HIP_TRY(ctx, launch_eval_index(
+                         ctx->d_idx,
+                         reinterpret_cast<const uint32_t *>(ctx->d_tie + tie_bits_offset(ctx->m)),
+                         ctx->any_tie, ctx->n, ctx->m, ctx->W, ctx->wpad, e, s));
     else
         HIP_TRY(ctx, launch_eval_direct(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, e, s));
     return EBIC_OK;
