@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libebic.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["ebic_kernels.hip", "ebic_batch_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
+SOURCES = ["ebic_kernels.hip", "ebic_index.hip", "ebic_batch_kernels.hip", "ebic_runtime.cpp", "ebic_evolve.cpp", "ebic_batch.cpp",
            "ebic_mlp_kernels.hip", "ebic_mlp.cpp", "ebic_surrogate.cpp", "ebic_scores.hip",
            "ebic_checkpoint.cpp", "ebic_noalloc.hip", "ebic_steps.hip",
            "ebic_mlp_fused.hip"]

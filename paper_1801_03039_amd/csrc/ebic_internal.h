@@ -47,6 +47,17 @@ hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m
                               int64_t wpad, uint64_t *idx, uint8_t *tie, int32_t *any_tie,
                               uint32_t *tbits, hipStream_t stream);
 
+// The same index built from per-row ranks (ebic_index.hip) for matrices of
+// at most kRankMaxCols columns.  It needs a device scratch of
+// index_ranked_scratch_bytes(n, m, W) bytes (0: the matrix is too wide),
+// which the caller keeps alive until the launches have completed.
+constexpr int32_t kRankMaxCols = 2048;
+size_t index_ranked_scratch_bytes(int64_t n, int32_t m, int64_t W);
+hipError_t launch_index_build_ranked(const float *a, int64_t n, int64_t npad, int32_t m,
+                                     int64_t W, int64_t wpad, uint64_t *idx, uint8_t *tie,
+                                     int32_t *any_tie, uint32_t *tbits, void *scratch,
+                                     hipStream_t stream);
+
 struct EvalArgs {
     const int32_t *offsets;
     const int32_t *cols;

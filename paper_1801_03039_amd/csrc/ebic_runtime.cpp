@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,6 +102,18 @@ int64_t index_bytes_for(int32_t m, int64_t wpad) {
     return (int64_t)m * (int64_t)m * (wpad * 8 + 1);  // order words + tie flags
 }
 
+struct BuildScratch {
+    std::mutex mu;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+BuildScratch &build_scratch(int device) {
+    constexpr int kDevices = 64;
+    static BuildScratch per_device[kDevices];
+    return per_device[device < 0 || device >= kDevices ? 0 : device];
+}
+
 ebic_status build_index(ebic_ctx *ctx) {
     if (ctx->idx_built) return EBIC_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -122,14 +135,41 @@ ebic_status build_index(ebic_ctx *ctx) {
         }
         ctx->d_tie = static_cast<uint8_t *>(p);
     }
+    // The rank-based build needs a scratch (ranks and bit-planes), shared by
+    // every build on the device and held until the process ends; a build
+    // holds it until its launches have completed.  Without it (a matrix
+    // wider than the ranked build takes, or no memory) the direct build runs.
+    BuildScratch &bs = build_scratch(ctx->device);
+    std::lock_guard<std::mutex> lock(bs.mu);
+    const size_t need = index_ranked_scratch_bytes(ctx->n, ctx->m, ctx->W);
+    if (need > bs.bytes) {
+        if (bs.ptr) {
+            (void)hipFree(bs.ptr);
+            bs.ptr = nullptr;
+            bs.bytes = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, need) == hipSuccess) {
+            bs.ptr = p;
+            bs.bytes = need;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    const bool ranked = need > 0 && need <= bs.bytes;
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
     int32_t *d_any = reinterpret_cast<int32_t *>(ctx->d_tie + tie_flag_offset(ctx->m));
     uint32_t *d_bits = reinterpret_cast<uint32_t *>(ctx->d_tie + tie_bits_offset(ctx->m));
-    HIP_TRY(ctx, launch_index_build(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, ctx->wpad,
-                                    ctx->d_idx, ctx->d_tie, d_any, d_bits, ctx->stream));
+    if (ranked)
+        HIP_TRY(ctx, launch_index_build_ranked(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W,
+                                               ctx->wpad, ctx->d_idx, ctx->d_tie, d_any, d_bits,
+                                               bs.ptr, ctx->stream));
+    else
+        HIP_TRY(ctx, launch_index_build(ctx->d_a, ctx->n, ctx->npad, ctx->m, ctx->W, ctx->wpad,
+                                        ctx->d_idx, ctx->d_tie, d_any, d_bits, ctx->stream));
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(e1));
     float ms = 0.f;

@@ -110,13 +110,14 @@ def test_ingest_layouts_match_oracle(E, n, m, source):
 
 
 @pytest.mark.parametrize("n,m", [(1, 1), (65, 15), (1025, 16), (1100, 17), (3000, 40),
-                                 (16 * 64 * 3 + 1, 33)])
+                                 (16 * 64 * 3 + 1, 33), (64 * 64 + 200, 40), (700, 65)])
 @pytest.mark.parametrize("kind", ["normal", "adversarial"])
 def test_index_every_ordered_pair(E, n, m, kind):
     # Series (p, q) for every ordered pair, p = q included: the rising mask
     # is order row (p, q) of the index word for word, the falling mask
-    # order row (q, p).  Sizes cross the build's 1024-row blocks and its
-    # 16-column groups.
+    # order row (q, p).  Sizes cross the 16-column groups and 64-word blocks
+    # of the rank-based build, its padded row widths (16, 32, 64, 128
+    # slots) and odd word counts.
     rng = np.random.default_rng(n + 7 * m)
     a = (rng.standard_normal((n, m)).astype(np.float32) if kind == "normal"
          else synth.adversarial_matrix(rng, n, m))
@@ -211,3 +212,92 @@ def test_auto_falls_back_to_direct_over_budget(E):
         # a budget lowered after the build sends AUTO back to the direct kernel
         ctx.set_index_budget(0)
         assert ctx.evaluate(off, cols, **kw)["counts"].tolist() == ref["counts"].tolist()
+
+
+def _pair_reference(a, P, Q, sigma):
+    """Masks, counts and Eq. (1) fitness of the length-2 series (P[i], Q[i])
+    with exact rising and falling trends, straight from the definition:
+    rising rows have a[r,p] < a[r,q], falling rows a[r,p] > a[r,q]."""
+    n = a.shape[0]
+    W = (n + 63) // 64
+    up = a[:, P] < a[:, Q]
+    dn = a[:, P] > a[:, Q]
+    bits = np.zeros((2, W * 64, len(P)), dtype=bool)
+    bits[0, :n] = up
+    bits[1, :n] = dn
+    masks = np.packbits(bits.transpose(2, 0, 1), axis=2, bitorder="little").view(np.uint64)
+    counts = (up | dn).sum(axis=0).astype(np.int32)
+    fit = np.array([oracle.fitness(int(c), 2, sigma) for c in counts], dtype=np.float64)
+    return masks, counts, fit
+
+
+def _check_pairs(E, ctx, a, P, Q, sigma):
+    import torch
+    dev = torch.device("cuda:0")
+    series = np.stack([P, Q], axis=1).astype(np.int32)
+    off = np.arange(0, 2 * len(P) + 1, 2, dtype=np.int32)
+    cols = series.reshape(-1)
+    cnt = torch.empty(len(P), dtype=torch.int32, device=dev)
+    fit = torch.empty(len(P), dtype=torch.float64, device=dev)
+    masks = torch.empty((len(P), 2, ctx.W), dtype=torch.int64, device=dev)
+    ctx.evaluate_device(torch.from_numpy(off).to(dev), torch.from_numpy(cols).to(dev), cnt, fit,
+                        masks, sigma=sigma, max_violations=0, negative_trends=True)
+    torch.cuda.synchronize()
+    ref_m, ref_c, ref_f = _pair_reference(a, P, Q, sigma)
+    assert np.array_equal(masks.cpu().numpy().view(np.uint64), ref_m)
+    assert np.array_equal(cnt.cpu().numpy(), ref_c)
+    assert np.array_equal(fit.cpu().numpy().view(np.int64), ref_f.view(np.int64))
+
+
+def test_index_ties_confined_to_some_words(E):
+    # Two 64-word blocks of rows: a tie and a NaN sit in words of the first
+    # block, the second has neither, so both the tie-aware and the
+    # complement form of the rank-based build run in one matrix.  Every
+    # ordered pair is checked against the definition, and the matrix
+    # reports a tied pair.
+    rng = np.random.default_rng(21)
+    n, m = 64 * 64 + 300, 40
+    a = rng.standard_normal((n, m)).astype(np.float32)
+    a[200, 7] = a[200, 22]          # word 3: a tie between columns 7 and 22
+    a[700, 5] = np.float32("nan")   # word 10: a NaN in column 5
+    a[701, 9] = np.float32(-0.0)    # signed zeros compare equal
+    a[701, 30] = np.float32(0.0)
+    P, Q = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    P, Q = P.reshape(-1), Q.reshape(-1)
+    with E.Context(a, path="index") as ctx:
+        _note(f"ties in some words n={n} m={m}")
+        _check_pairs(E, ctx, a, P, Q, sigma=7)
+        assert ctx.info()["index_ties"] == 1
+    b = rng.standard_normal((n, m)).astype(np.float32)
+    any_tie = any(np.any(b[:, p] == b[:, q]) for p in range(m) for q in range(p + 1, m))
+    with E.Context(b, path="index") as ctx:
+        _note(f"tie-free n={n} m={m}")
+        _check_pairs(E, ctx, b, P, Q, sigma=7)
+        assert ctx.info()["index_ties"] == int(any_tie)
+
+
+@pytest.mark.parametrize("m", [200, 1025, 2048, 2049])
+def test_index_wide_matrices_sampled_pairs(E, m):
+    # Wide matrices: 1025-2048 columns take the rank build's 32 keys per
+    # lane, 2049 the direct ballot build.  Pairs are sampled (all pairs of
+    # the first 40 columns, pairs with the last column, random pairs), with
+    # ties and a NaN planted in the first word and an odd word count.
+    rng = np.random.default_rng(m)
+    n = 64 * 2 + 17
+    a = rng.standard_normal((n, m)).astype(np.float32)
+    a[5, 3] = a[5, m - 1]
+    a[9, m // 2] = np.float32("nan")
+    a[70, 1] = a[70, 2]
+    P, Q = np.meshgrid(np.arange(40), np.arange(40), indexing="ij")
+    P, Q = list(P.reshape(-1)), list(Q.reshape(-1))
+    for p in range(0, m, max(1, m // 64)):
+        P += [p, m - 1]
+        Q += [m - 1, p]
+    P += list(rng.integers(0, m, 20000))
+    Q += list(rng.integers(0, m, 20000))
+    P = np.array(P, dtype=np.int64)
+    Q = np.array(Q, dtype=np.int64)
+    with E.Context(a, path="index") as ctx:
+        _note(f"wide m={m} n={n}")
+        _check_pairs(E, ctx, a, P, Q, sigma=7)
+        assert ctx.info()["index_ties"] == 1
