@@ -495,6 +495,50 @@ hipError_t launch_planes_compare(const uint16_t *rank, const uint32_t *wflag, in
 
 }  // namespace
 
+namespace {
+template <int LOGM>
+hipError_t resolve_rank() {
+    hipFuncAttributes fa;
+    return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&index_rank_kernel<LOGM>));
+}
+template <int NB>
+hipError_t resolve_planes_compare() {
+    hipFuncAttributes fa;
+    hipError_t e =
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&index_planes_kernel<NB>));
+    if (e != hipSuccess) return e;
+    return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&index_compare_kernel<NB>));
+}
+}  // namespace
+
+hipError_t index_ranked_prepare(int32_t m) {
+    if (m < 1 || m > kRankMaxCols) return hipErrorInvalidValue;
+    const RankedLayout L = ranked_layout(1, m, 1);
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&index_init_kernel));
+    if (e != hipSuccess) return e;
+    switch (L.logm) {
+    case 4: e = resolve_rank<4>(); break;
+    case 5: e = resolve_rank<5>(); break;
+    case 6: e = resolve_rank<6>(); break;
+    case 7: e = resolve_rank<7>(); break;
+    case 8: e = resolve_rank<8>(); break;
+    case 9: e = resolve_rank<9>(); break;
+    case 10: e = resolve_rank<10>(); break;
+    case 11: e = resolve_rank<11>(); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    switch (L.nb) {
+    case 4: return resolve_planes_compare<4>();
+    case 6: return resolve_planes_compare<6>();
+    case 8: return resolve_planes_compare<8>();
+    case 10: return resolve_planes_compare<10>();
+    case 12: return resolve_planes_compare<12>();
+    default: return hipErrorInvalidValue;
+    }
+}
+
 size_t index_ranked_scratch_bytes(int64_t n, int32_t m, int64_t W) {
     if (m < 1 || m > kRankMaxCols) return 0;
     return ranked_layout(n, m, W).bytes;

@@ -53,6 +53,9 @@ hipError_t launch_index_build(const float *a, int64_t n, int64_t npad, int32_t m
 // which the caller keeps alive until the launches have completed.
 constexpr int32_t kRankMaxCols = 2048;
 size_t index_ranked_scratch_bytes(int64_t n, int32_t m, int64_t W);
+// Resolves the ranked build's kernels for m columns (their code is loaded on
+// first use), so that a timed build measures the launches alone.
+hipError_t index_ranked_prepare(int32_t m);
 hipError_t launch_index_build_ranked(const float *a, int64_t n, int64_t npad, int32_t m,
                                      int64_t W, int64_t wpad, uint64_t *idx, uint8_t *tie,
                                      int32_t *any_tie, uint32_t *tbits, void *scratch,

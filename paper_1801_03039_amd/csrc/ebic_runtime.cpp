@@ -157,6 +157,7 @@ ebic_status build_index(ebic_ctx *ctx) {
         }
     }
     const bool ranked = need > 0 && need <= bs.bytes;
+    if (ranked) HIP_TRY(ctx, index_ranked_prepare(ctx->m));
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
