@@ -29,6 +29,7 @@ struct ebic_mlp {
     float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
     uint16_t *W1b = nullptr, *W2b = nullptr, *w3b = nullptr;
     int64_t step = 0;
+    int32_t last_B = 0;   // batch of the last training call (its loss is in sq)
     // per-batch buffers (capacity cap_B candidates, cap_L column entries)
     int64_t cap_B = 0, cap_L = 0;
     int32_t *off = nullptr, *cols = nullptr, *occ_start = nullptr, *occ_pos = nullptr,
@@ -576,11 +577,28 @@ ebic_status ebic_mlp_train(ebic_mlp *m, const int32_t *offsets, const int32_t *c
                        m->cfg.beta2, m->cfg.eps, c1, c2, m->stream));
         if ((st = refresh_bf16(m)) != EBIC_OK) return st;
     }
+    m->last_B = B;
+    if (!loss) return EBIC_OK;   // the steps stay queued on the network's stream
     const float l = host_loss(m, B, &st);  // loss before the last step
     if (st != EBIC_OK) return st;
-    if (loss) *loss = l;
+    *loss = l;
     return EBIC_OK;
 }
+
+}  // extern "C"
+
+namespace ebic {
+ebic_status mlp_last_loss(ebic_mlp *m, float *loss) {
+    if (!m || !loss || m->last_B < 1) return mfail(EBIC_E_STATE, "no training call to report");
+    MHIP(hipSetDevice(m->device));
+    ebic_status st = EBIC_OK;
+    const float l = host_loss(m, m->last_B, &st);
+    if (st == EBIC_OK) *loss = l;
+    return st;
+}
+}  // namespace ebic
+
+extern "C" {
 
 ebic_status ebic_mlp_train_step(ebic_mlp *m, const int32_t *offsets, const int32_t *cols,
                                 int32_t B, const float *target, float *loss) {

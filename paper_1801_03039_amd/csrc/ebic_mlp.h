@@ -5,7 +5,16 @@
 
 #include <cstdint>
 
+#include "../../include/ebic.h"
+
+struct ebic_mlp;
+
 namespace ebic {
+
+// Loss of the last ebic_mlp_train call before its last step (waits for the
+// steps that call queued when it was made without a loss pointer).
+ebic_status mlp_last_loss(ebic_mlp *m, float *loss);
+
 namespace mlp {
 
 // C[M x N] = sum_k A(m,k) B(k,n), BF16 operands by strides, FP32 result.

@@ -8,7 +8,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -141,6 +145,82 @@ struct Pop {
     }
 };
 
+// Helper threads kept for the whole run: run(n, f) calls f(0) .. f(n - 1)
+// on them and on the calling thread, and returns once every call has
+// finished.  A helper that cannot be started is left out (the calling
+// thread drains whatever remains).
+class Helpers {
+  public:
+    explicit Helpers(int32_t threads) {
+        for (int32_t t = 1; t < threads; ++t) {
+            try {
+                th_.emplace_back([this] { loop(); });
+            } catch (...) {
+                break;
+            }
+        }
+    }
+    ~Helpers() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (std::thread &t : th_) t.join();
+    }
+    Helpers(const Helpers &) = delete;
+    Helpers &operator=(const Helpers &) = delete;
+
+    void run(int32_t n, const std::function<void(int32_t)> &f) {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            job_ = &f;
+            n_ = n;
+            next_.store(0);
+            busy_ = (int32_t)th_.size();
+            ++epoch_;
+        }
+        cv_.notify_all();
+        drain(f, n);
+        std::unique_lock<std::mutex> g(mu_);
+        done_.wait(g, [this] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void drain(const std::function<void(int32_t)> &f, int32_t n) {
+        for (int32_t i; (i = next_.fetch_add(1)) < n;) f(i);
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int32_t)> *f;
+            int32_t n;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return stop_ || epoch_ != seen; });
+                if (stop_) return;
+                seen = epoch_;
+                f = job_;
+                n = n_;
+            }
+            drain(*f, n);
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                if (--busy_ == 0) done_.notify_one();
+            }
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int32_t)> *job_ = nullptr;
+    int32_t n_ = 0, busy_ = 0;
+    std::atomic<int32_t> next_{0};
+    uint64_t epoch_ = 0;
+    bool stop_ = false;
+};
+
 // Tabu list: every series ever analysed, exact and ordered.  Series live in
 // an append-only arena; the set holds (offset, length) keys into it.
 class Tabu {
@@ -166,6 +246,15 @@ class Tabu {
     }
 
     size_t size() const { return used_; }
+    static uint64_t hash(const int32_t *p, int32_t L) {
+        uint64_t h = 0x84222325cbf29ce4ull ^ (uint64_t)L;
+        for (int32_t i = 0; i < L; ++i) {
+            h ^= (uint32_t)p[i];
+            h *= 0x100000001b3ull;
+            h ^= h >> 29;
+        }
+        return h ^ (h >> 32);
+    }
     // The set as its series in insertion order (the arena and each entry's
     // length); loading re-inserts them.
     void save(Writer &w) const {
@@ -201,15 +290,6 @@ class Tabu {
         size_t at = 0;
         int32_t len = -1;   // -1: empty
     };
-    static uint64_t hash(const int32_t *p, int32_t L) {
-        uint64_t h = 0x84222325cbf29ce4ull ^ (uint64_t)L;
-        for (int32_t i = 0; i < L; ++i) {
-            h ^= (uint32_t)p[i];
-            h *= 0x100000001b3ull;
-            h ^= h >> 29;
-        }
-        return h ^ (h >> 32);
-    }
     // Slot holding the series, or the empty slot where it would go.
     size_t find(const int32_t *s, int32_t L, uint64_t h) const {
         const size_t mask = slots_.size() - 1;
@@ -726,35 +806,76 @@ class Run {
         struct Share {
             uint64_t seed = 0;
             Pop pop;
+            Tabu mine;                   // the share's own series
+            std::vector<uint64_t> hash;  // hash of each of its series
             int64_t hits = 0;
         };
         std::vector<Share> shares((size_t)kScreenShares);
         for (Share &sh : shares) sh.seed = br_.rng.next();
-        auto draw = [&](int32_t j) {
+        if (!helpers_) {
+            if (threads <= 0) threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
+            helpers_ = std::make_unique<Helpers>(std::max(1, std::min(threads, kScreenShares)));
+        }
+        helpers_->run(kScreenShares, [&](int32_t j) {
             Share &sh = shares[(size_t)j];
             const int64_t quota = target / kScreenShares + (j < target % kScreenShares ? 1 : 0);
             Breeder b(p_, M_, sh.seed);
             b.penalty = br_.penalty;
-            Tabu mine;
             while (sh.pop.size() < quota) {
                 b.make_child(prev_);
                 const int32_t L = (int32_t)b.child.size();
-                if (tabu_.contains(b.child.data(), L) || !mine.insert(b.child.data(), L)) {
+                if (tabu_.contains(b.child.data(), L) || !sh.mine.insert(b.child.data(), L)) {
                     if (++sh.hits > limit) return;
                     continue;
                 }
                 sh.pop.push(b.child.data(), L);
                 b.add_penalty(b.child.data(), L);
             }
+        });
+        // Join in share order; a series that an earlier share holds is a
+        // repeat.  Hashes are taken in parallel, then one pass over a flat
+        // table of (hash, share, index) keeps each series' first copy.
+        helpers_->run(kScreenShares, [&](int32_t j) {
+            Share &sh = shares[(size_t)j];
+            sh.hash.resize((size_t)sh.pop.size());
+            for (int32_t i = 0; i < sh.pop.size(); ++i)
+                sh.hash[(size_t)i] = Tabu::hash(sh.pop.series(i), sh.pop.len(i));
+        });
+        struct Ref {
+            uint64_t h;
+            int32_t share, i;   // share -1: empty
         };
-        run_shares(kScreenShares, threads, draw);
+        int64_t total = 0;
+        for (const Share &sh : shares) total += sh.pop.size();
+        size_t cap = 1024;
+        while (cap < (size_t)(2 * total + 2 * need)) cap *= 2;
+        std::vector<Ref> table(cap, Ref{0, -1, 0});
+        // share kScreenShares: a child of the top-up, by its index in the pool
+        auto series_of = [&](const Ref &r) -> std::pair<const int32_t *, int32_t> {
+            const Pop &pp = r.share == kScreenShares ? pool_ : shares[(size_t)r.share].pop;
+            return {pp.series(r.i), pp.len(r.i)};
+        };
+        // Inserts (h, share, i) unless the series is present; false if present.
+        auto insert = [&](uint64_t h, const int32_t *c, int32_t L, int32_t share, int32_t i) {
+            for (size_t k = (size_t)h & (cap - 1);; k = (k + 1) & (cap - 1)) {
+                Ref &r = table[k];
+                if (r.share < 0) {
+                    r = Ref{h, share, i};
+                    return true;
+                }
+                if (r.h != h) continue;
+                const auto o = series_of(r);
+                if (o.second == L && std::memcmp(o.first, c, sizeof(int32_t) * (size_t)L) == 0)
+                    return false;
+            }
+        };
         int64_t hits = 0;
         pool_.clear();
-        Tabu pooled;
-        for (const Share &sh : shares) {
+        for (int32_t j = 0; j < kScreenShares; ++j) {
+            const Share &sh = shares[(size_t)j];
             hits += sh.hits;
             for (int32_t i = 0; i < sh.pop.size(); ++i) {
-                if (pooled.insert(sh.pop.series(i), sh.pop.len(i)))
+                if (insert(sh.hash[(size_t)i], sh.pop.series(i), sh.pop.len(i), j, i))
                     pool_.push(sh.pop.series(i), sh.pop.len(i));
                 else
                     ++hits;
@@ -764,24 +885,35 @@ class Run {
         while (hits <= limit && pool_.size() < need) {
             br_.make_child(prev_);
             const int32_t L = (int32_t)child.size();
-            if (tabu_.contains(child.data(), L) || !pooled.insert(child.data(), L)) {
+            if (tabu_.contains(child.data(), L)) {
                 ++hits;
                 continue;
             }
             pool_.push(child.data(), L);
+            const int32_t at = pool_.size() - 1;
+            if (!insert(Tabu::hash(child.data(), L), pool_.series(at), L, kScreenShares, at)) {
+                pool_.cols.resize((size_t)pool_.off[(size_t)at]);   // a repeat: drop it
+                pool_.off.pop_back();
+                ++hits;
+            }
         }
         if (hits > limit) {
             stopped_ = true;
             return false;
         }
         auto sc = score(pool_);      // one float or double per pooled child
+        // The `need` highest scores, ties to the earlier child, kept in pool
+        // order (NaN ranks last).
         std::vector<int32_t> order((size_t)pool_.size());
         for (int32_t i = 0; i < pool_.size(); ++i) {
             order[(size_t)i] = i;
-            if (sc[(size_t)i] != sc[(size_t)i]) sc[(size_t)i] = -INFINITY;  // NaN ranks last
+            if (sc[(size_t)i] != sc[(size_t)i]) sc[(size_t)i] = -INFINITY;
         }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return sc[(size_t)a] > sc[(size_t)b]; });
+        auto before = [&](int32_t a, int32_t b) {
+            return sc[(size_t)a] > sc[(size_t)b] || (sc[(size_t)a] == sc[(size_t)b] && a < b);
+        };
+        if ((size_t)need < order.size())
+            std::nth_element(order.begin(), order.begin() + need, order.end(), before);
         order.resize((size_t)need);
         std::sort(order.begin(), order.end());
         for (int32_t i : order) {
@@ -795,30 +927,6 @@ class Run {
     Run &operator=(const Run &) = delete;
 
   private:
-    // Runs f(0) .. f(n - 1) on up to `threads` threads (0: the hardware's).
-    template <typename F>
-    static void run_shares(int32_t n, int32_t threads, F &&f) {
-        if (threads <= 0) threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
-        threads = std::max(1, std::min(threads, n));
-        // the calling thread takes shares too, so the loop drains even if a
-        // helper thread cannot be started
-        std::atomic<int32_t> next{0};
-        auto drain = [&] {
-            for (int32_t i; (i = next.fetch_add(1)) < n;) f(i);
-        };
-        std::vector<std::thread> pool;
-        for (int32_t t = 1; t < threads; ++t) {
-            try {
-                pool.emplace_back(drain);
-            } catch (...) {
-                break;
-            }
-        }
-        drain();
-        for (std::thread &th : pool) th.join();
-    }
-
-  private:
     const ebic_evolve_params p_;
     const int32_t M_;
     const int32_t generations_;
@@ -827,6 +935,7 @@ class Run {
     TopRank toprank_;
     std::vector<int32_t> s_;
     Pop prev_, cur_, pool_;
+    std::unique_ptr<Helpers> helpers_;   // pool drawing threads, started on first use
     ebic_params evalp_{};
     int32_t tabu_limit_ = 0;
     int32_t gen_ = 0, first_ = 0, gens_run_ = 0;

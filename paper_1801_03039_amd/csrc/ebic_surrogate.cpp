@@ -9,6 +9,7 @@
 #include <numeric>
 #include <vector>
 
+#include "ebic_mlp.h"
 #include "ebic_run.h"
 
 using namespace ebic::host;
@@ -124,6 +125,29 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
     std::vector<int32_t> pool_off, pool_cols;   // the last screened pool
     std::vector<float> pool_pred;
 
+    // The report of a generation waits for its training loss, which is read
+    // once the next generation has drawn its pool (the training runs on the
+    // GPU meanwhile) or after the last generation.
+    struct Report {
+        bool due = false, trained = false;
+        int32_t gen = 0, screened = 0, pool = 0;
+        double corr = NAN;
+    } report;
+    auto flush = [&]() -> ebic_status {
+        if (!report.due) return EBIC_OK;
+        report.due = false;
+        double loss = 0.0;
+        if (report.trained) {
+            float l = 0.f;
+            const ebic_status e = ebic::mlp_last_loss(net, &l);
+            if (e != EBIC_OK) return e;
+            loss = l;
+        }
+        if (sp->on_surrogate)
+            sp->on_surrogate(sp->user, report.gen, report.screened, report.corr, loss, report.pool);
+        return EBIC_OK;
+    };
+
     for (;;) {
         const int32_t gen = run.generation();
         const bool screen = gen > sp->warmup_generations && have_corr && last_corr >= sp->min_rank_corr;
@@ -133,6 +157,7 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
             const int32_t need = params->population - run.elites();
             more = run.next_screened(sp->oversample, [&](const Pop &pl) {
                 rebase(pl, 0, pool_off, pool_cols);
+                if ((score_st = flush()) != EBIC_OK) return std::vector<float>((size_t)pl.size());
                 std::vector<float> s((size_t)pl.size(), -INFINITY);
                 pool = pl.size();
                 ebic_status e = ebic_mlp_predict(net, pool_off.data(), pool_cols.data(),
@@ -146,9 +171,12 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
                 // below them.
                 std::vector<int32_t> order((size_t)pl.size());
                 std::iota(order.begin(), order.end(), 0);
-                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-                    return s[(size_t)a] > s[(size_t)b];
-                });
+                // the `keep` best predictions, ties to the earlier child
+                std::nth_element(order.begin(), order.begin() + keep, order.end(),
+                                 [&](int32_t a, int32_t b) {
+                                     return s[(size_t)a] > s[(size_t)b] ||
+                                            (s[(size_t)a] == s[(size_t)b] && a < b);
+                                 });
                 order.resize((size_t)keep);
                 std::sort(order.begin(), order.end());
                 std::vector<int32_t> ro(1, 0), rc, rcnt((size_t)keep);
@@ -176,6 +204,7 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
             more = run.next();
         }
         if (!more) break;
+        if ((st = flush()) != EBIC_OK) return st;
         const Pop &pop = run.pending();
         const int32_t first = run.first_new();
         const int32_t n = pop.size() - first;
@@ -235,7 +264,7 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
         for (int32_t i = 0; i < n; ++i) bt.target[(size_t)i] = (float)std::log1p(fit[(size_t)i]);
         if (n > 0) replay.push_back(std::move(bt));
         while ((int32_t)replay.size() > sp->replay_generations) replay.pop_front();
-        double loss = 0.0;
+        bool trained = false;
         if (!replay.empty() && sp->train_steps > 0) {
             Batch all;
             all.off.push_back(0);
@@ -246,19 +275,18 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
                 all.target.insert(all.target.end(), b.target.begin(), b.target.end());
             }
             const int32_t B = (int32_t)all.target.size();
-            float l = 0.f;
             if ((st = ebic_mlp_train(net, all.off.data(), all.cols.data(), B, all.target.data(),
-                                     sp->train_steps, &l)) != EBIC_OK)
+                                     sp->train_steps, nullptr)) != EBIC_OK)
                 return st;
-            loss = l;
+            trained = true;
         }
         if (checked) {
             last_corr = corr;
             have_corr = true;
         }
-        if (sp->on_surrogate)
-            sp->on_surrogate(sp->user, gen, screen ? 1 : 0, checked ? corr : NAN, loss, pool);
+        report = Report{true, trained, gen, screen ? 1 : 0, pool, checked ? corr : NAN};
     }
+    if ((st = flush()) != EBIC_OK) return st;
 
     // Steps 6-7 with the expansion parameters.
     const int64_t W = ebic_mask_words(info.n_rows);
