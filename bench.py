@@ -556,7 +556,7 @@ def run_surrogate(args):
         "roofline": {"bound": "mfma", "achieved": round(flops / t_step / 1e12, 3),
                      "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(flops / t_step / 1e12 / 2500.0, 5), "traffic": None,
-                     "kernel": "MLP training step (gemm_bf16_kernel and its companions)",
+                     "kernel": "MLP training step (mlp_rows_kernel, mlp_grads_kernel, mlp_update_kernel)",
                      "flops_per_step": flops, "ms_per_step": round(t_step * 1e3, 3),
                      "batch": B},
         "cpu_baseline": cpu,

@@ -58,8 +58,11 @@ enum { EBIC_ROW_MAJOR = 0, EBIC_COL_MAJOR = 1 };
  *           holds for every ordered column pair (p, q) the 64-row bitmasks
  *           of rows with a[r,p] < a[r,q]; evaluation then combines one
  *           64-bit word per consecutive pair and 64 rows.  Uses
- *           n_cols^2 * ceil(n_rows/64) * 8 bytes of device memory and
- *           supports max_violations <= 3 (larger tolerances use DIRECT).
+ *           n_cols^2 * (wpad * 8 + 1) bytes of device memory (wpad =
+ *           ceil(n_rows/64) rounded up to 16), plus a build scratch of
+ *           ranks and bit-planes (about n_rows * n_cols * 3.7 bytes for up
+ *           to 2048 columns) that the library keeps per device and reuses,
+ *           and supports max_violations <= 3 (larger tolerances use DIRECT).
  *   AUTO:   INDEX when it fits the context's index budget, else DIRECT. */
 enum { EBIC_PATH_AUTO = 0, EBIC_PATH_DIRECT = 1, EBIC_PATH_INDEX = 2 };
 

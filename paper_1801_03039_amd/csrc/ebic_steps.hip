@@ -60,11 +60,6 @@ __device__ __forceinline__ uint64_t rl64(uint64_t v, int lane) {
 __device__ __forceinline__ double rlf64(double v, int lane) {
     return __longlong_as_double((long long)rl64((uint64_t)__double_as_longlong(v), lane));
 }
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // x % n.  For n < 2^16 the 64-bit value is reduced Horner-style in 16-bit
 // digits with three 32-bit remainders (each partial value stays below
