@@ -209,10 +209,12 @@ ebic_status ebic_evolve_surrogate(ebic_ctx *ctx, uint64_t seed, int32_t generati
         const int32_t first = run.first_new();
         const int32_t n = pop.size() - first;
         rebase(pop, first, off, cols);
-        // The model's view of the new members before their exact scores.
+        // The model's view of the new members before their exact scores
+        // (the rank check of a plainly bred generation; a screened one is
+        // checked on a sample of its pool).
         double corr = 0.0;
         bool checked = false;
-        if (gen > 0 && n > 0) {
+        if (gen > 0 && n > 0 && !(screen && pool > 0 && sp->check_sample > 0)) {
             pred.assign((size_t)n, 0.f);
             if ((st = ebic_mlp_predict(net, off.data(), cols.data(), n, pred.data())) != EBIC_OK)
                 return st;
