@@ -399,13 +399,19 @@ void ebic_run_destroy(ebic_run *r);
  * draining a tile queue, launched directly or as a captured HIP graph; the
  * run table lives in device memory and is refreshed each generation.  The
  * host steps of the runs proceed on host threads.  Evaluation uses each run's
- * pairwise order index (built at creation), so max_violations <= 3.
+ * pairwise order index (built at creation) for max_violations <= 3.  A run
+ * whose index exceeds its context's budget (ebic_set_index_budget's
+ * default) or does not fit in device memory has none; such runs, and every
+ * run when max_violations > 3, are evaluated by the direct kernel, one
+ * launch per run after the batched launch on the batch's stream.  Results
+ * are the same either way.
  */
 typedef struct ebic_batch ebic_batch;
 
 /* matrices[r]: host row-major n_rows[r] x n_cols[r] FP32 (copied; the
  * caller may free them on return).  Errors: E_ARG (n_runs < 1, null or bad
- * sizes), E_NOMEM (a matrix or its order index does not fit), E_DEVICE. */
+ * sizes), E_NOMEM (a matrix does not fit; an order index that does not fit
+ * leaves its run to the direct kernel), E_DEVICE. */
 ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, const int64_t *n_rows,
                               const int32_t *n_cols, int32_t device, ebic_batch **out);
 ebic_status ebic_batch_destroy(ebic_batch *b);
@@ -492,7 +498,8 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
  * back and synchronises) sees each running run's population after its
  * evaluation.  In the stats, eval_ms is the device time of the whole
  * generation loop (steps and evaluations) plus the Steps 6-7 evaluation.
- * Errors: E_STATE if a run's tabu table fills up. */
+ * Every run needs its order index and max_violations <= 3 (E_ARG
+ * otherwise).  Errors: E_STATE if a run's tabu table fills up. */
 ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32_t generations,
                                      const ebic_evolve_params *params,
                                      ebic_batch_generation_fn on_generation, void *user,

@@ -34,6 +34,9 @@ struct ebic_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     std::vector<ebic_ctx *> ctx;
+    // 1: the run's matrix has no order index (over its budget, or no device
+    // memory for it); it is evaluated by the direct kernel
+    std::vector<uint8_t> direct;
     // device buffers
     IndexRun *d_runs = nullptr;          // run table, then the tile bases (one allocation)
     uint32_t *d_tile_base = nullptr;     // inside the d_runs allocation
@@ -160,21 +163,28 @@ size_t run_table_bytes(int32_t n_runs) {
 // whose candidates take at most 256 lanes each gets tiles of whole
 // candidates (as many as fit); other runs, or all without it, get tiles of
 // 256 consecutive (candidate, word-group) items.
+// Whether run r of request q is evaluated by the batched index kernel (else
+// by the direct kernel after it).
+bool via_index(const ebic_batch *b, const Request &q, int32_t r) {
+    return !b->direct[(size_t)r] && q.params->max_violations <= kIndexMaxViolations;
+}
+
 uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words, int32_t whole) {
     const int32_t R = (int32_t)b->ctx.size();
     int64_t cand = 0, maskw = 0;
     uint64_t tiles = 0;
     for (int32_t r = 0; r < R; ++r) {
         ebic_ctx *c = b->ctx[(size_t)r];
-        const int32_t P = q.P[(size_t)r];
+        // a directly evaluated run keeps its place in the launch but gets no tiles
+        const int32_t P = via_index(b, q, r) ? q.P[(size_t)r] : 0;
         const uint64_t items = (uint64_t)((c->W + words - 1) / words);
         const int32_t cpw = (whole && items <= 256) ? (int32_t)(256 / items) : 0;
         b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
                                 maskw, cpw, 0};
         b->h_tile_base[r] = (uint32_t)tiles;
         tiles += cpw ? ((uint64_t)P + cpw - 1) / cpw : ((uint64_t)P * items + 255) / 256;
-        cand += P;
-        if (q.masks) maskw += (int64_t)P * 2 * c->W;
+        cand += q.P[(size_t)r];
+        if (q.masks) maskw += (int64_t)q.P[(size_t)r] * 2 * c->W;
     }
     b->h_tile_base[R] = (uint32_t)tiles;
     return tiles;
@@ -277,11 +287,17 @@ ebic_status time_replays(ebic_batch *b, int32_t reps, double *ms_per_launch) {
 
 // Runs one packed request (CBF already in h_off/h_cols, P per run set).
 // Results land in h_counts/h_fit (and d_masks when asked).
+// Runs evaluated directly (no index, or k above the index kernel's limit)
+// get one direct-kernel launch each after the batched launch, on the same
+// stream, over their slice of the packed CBF and outputs.
 ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int32_t unroll,
                         int32_t words, int32_t whole, bool copy_back = true) {
     b->has_last = false;
     const uint64_t tiles = fill_runs(b, q, words, whole);
-    if (tiles == 0) return EBIC_OK;
+    const int32_t R = (int32_t)b->ctx.size();
+    bool any_direct = false;
+    for (int32_t r = 0; r < R; ++r) any_direct |= q.P[(size_t)r] > 0 && !via_index(b, q, r);
+    if (tiles == 0 && !any_direct) return EBIC_OK;
     if (tiles > 0x7FFFFFFFull)
         return bfail(EBIC_E_ARG, "batched populations too large for one launch; split them");
     BHIP(hipMemcpyAsync(b->d_off, b->h_off, sizeof(int32_t) * (size_t)(q.n_cand + 1),
@@ -291,12 +307,37 @@ ebic_status run_request(ebic_batch *b, const Request &q, int32_t workgroups, int
     BHIP(hipMemcpyAsync(b->d_runs, b->h_runs, run_table_bytes((int32_t)b->ctx.size()),
                         hipMemcpyHostToDevice, b->stream));
     BHIP(hipEventRecord(b->ev0, b->stream));
-    const BatchLaunch L =
-        make_launch(b, q, workgroups < 0 ? -1 : std::max(1, workgroups), unroll, words, tiles);
-    ebic_status st = launch(b, L);
-    if (st != EBIC_OK) return st;
-    b->last_launch = L;
-    b->has_last = true;
+    if (tiles > 0) {
+        const BatchLaunch L =
+            make_launch(b, q, workgroups < 0 ? -1 : std::max(1, workgroups), unroll, words, tiles);
+        ebic_status st = launch(b, L);
+        if (st != EBIC_OK) return st;
+        b->last_launch = L;
+        b->has_last = true;
+    }
+    int64_t cand = 0, maskw = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        ebic_ctx *c = b->ctx[(size_t)r];
+        const int32_t P = q.P[(size_t)r];
+        if (P > 0 && !via_index(b, q, r)) {
+            EvalArgs e{};
+            e.offsets = b->d_off + cand;   // global column positions
+            e.cols = b->d_cols;
+            e.P = P;
+            e.n_entries = b->cap_cols;
+            e.sigma = q.params->sigma;
+            e.k = q.params->max_violations;
+            e.negative = q.params->negative_trends ? 1 : 0;
+            e.masks = q.masks ? b->d_masks + maskw : nullptr;
+            e.counts = b->d_counts + cand;
+            e.fitness = b->d_fit + cand;
+            e.logt = c->d_log;
+            e.acc = b->d_acc + cand;
+            BHIP(launch_eval_direct(c->d_a, c->n, c->npad, c->m, c->W, e, b->stream));
+        }
+        cand += P;
+        if (q.masks) maskw += (int64_t)P * 2 * c->W;
+    }
     BHIP(hipEventRecord(b->ev1, b->stream));
     if (copy_back) {
         BHIP(hipMemcpyAsync(b->h_counts, b->d_counts, sizeof(int32_t) * (size_t)q.n_cand,
@@ -480,11 +521,19 @@ ebic_status ebic_batch_create(int32_t n_runs, const float *const *matrices, cons
                                      device, &c);
         if (st != EBIC_OK) return cleanup(st);
         b->ctx.push_back(c);
-        st = ensure_index(c);
-        if (st != EBIC_OK) {
-            set_thread_error(c->err.c_str());
-            return cleanup(st);
+        // A matrix whose index exceeds its context's budget, or does not fit
+        // in device memory, is evaluated by the direct kernel instead.
+        uint8_t direct = c->idx_bytes > c->idx_budget ? 1 : 0;
+        if (!direct) {
+            st = ensure_index(c);
+            if (st == EBIC_E_NOMEM) {
+                direct = 1;
+            } else if (st != EBIC_OK) {
+                set_thread_error(c->err.c_str());
+                return cleanup(st);
+            }
         }
+        b->direct.push_back(direct);
     }
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
@@ -590,8 +639,6 @@ ebic_status ebic_batch_evaluate(ebic_batch *b, const int32_t *const *offsets,
     if (params->struct_size < sizeof(ebic_params)) return bfail(EBIC_E_ARG, "params struct_size");
     if (params->sigma < 0 || params->max_violations < 0)
         return bfail(EBIC_E_RANGE, "sigma and max_violations must be >= 0");
-    if (params->max_violations > kIndexMaxViolations)
-        return bfail(EBIC_E_ARG, "batched evaluation supports max_violations <= 3");
     if (params->want_masks && !masks) return bfail(EBIC_E_ARG, "want_masks needs masks");
     const int32_t R = (int32_t)b->ctx.size();
     Request q;
@@ -686,9 +733,6 @@ ebic_status ebic_batch_evolve(ebic_batch *b, const uint64_t *seeds, int32_t gene
         ebic_status st = check_params(params, b->ctx[(size_t)r]->n, b->ctx[(size_t)r]->m);
         if (st != EBIC_OK) return st;
     }
-    if (params->eval.max_violations > kIndexMaxViolations ||
-        params->expand.max_violations > kIndexMaxViolations)
-        return bfail(EBIC_E_ARG, "batched runs support max_violations <= 3");
     if (host_threads <= 0) host_threads = (int32_t)std::max(1u, std::thread::hardware_concurrency());
     BHIP(hipSetDevice(b->device));
     const auto t0 = std::chrono::steady_clock::now();
@@ -793,7 +837,11 @@ ebic_status ebic_batch_evolve_device(ebic_batch *b, const uint64_t *seeds, int32
     }
     if (params->eval.max_violations > kIndexMaxViolations ||
         params->expand.max_violations > kIndexMaxViolations)
-        return bfail(EBIC_E_ARG, "batched runs support max_violations <= 3");
+        return bfail(EBIC_E_ARG, "device-side steps support max_violations <= 3");
+    for (int32_t r = 0; r < R; ++r)
+        if (b->direct[(size_t)r])
+            return bfail(EBIC_E_ARG, "device-side steps need every run's order index (run " +
+                                         std::to_string(r) + " has none)");
     const int32_t P = params->population, slot = params->len_max, K = params->toplist_size;
     int64_t wsum = 0;
     for (int i = 0; i < 5; ++i) wsum += params->op_weight[i];

@@ -184,8 +184,7 @@ def test_batch_errors(E, mats):
         bad = [(np.array([0, 2]), np.array([0, 99])), None]
         with pytest.raises(E.EbicError):
             b.evaluate(bad, sigma=1)
-        with pytest.raises(E.EbicError):
-            b.evaluate([None, None], sigma=1, max_violations=4)
+        assert b.evaluate([None, None], sigma=1, max_violations=4) == [None, None]
         assert b.evaluate([None, None], sigma=1) == [None, None]
         with pytest.raises(E.EbicError):
             b.time_replays(3)          # the last request launched nothing
@@ -291,3 +290,52 @@ def test_batched_workload_shapes_one_generation(E):
         _note("batched workload shapes")
         got = b.evaluate(pops, sigma=25, tune=True)
     _check_runs([a for a, _ in data], pops, got, 25, 0, False, masks=False)
+
+
+def test_large_tolerance_batches_use_the_direct_kernel(E, mats):
+    # k above the index kernel's limit: every run is evaluated by the direct
+    # kernel after the (empty) batched launch, with the same results
+    rng = np.random.default_rng(31)
+    with E.Batch(mats) as b:
+        for k in (4, 7):
+            for neg in (False, True):
+                pops = _pops(rng, mats, skip=(1,))
+                _note(f"evaluate k={k} neg={neg}")
+                got = b.evaluate(pops, sigma=5, max_violations=k, negative_trends=neg,
+                                 want_masks=True)
+                _check_runs(mats, pops, got, 5, k, neg)
+
+
+def test_run_over_its_index_budget_is_evaluated_directly(E):
+    # A 60000 x 1200 matrix needs a 10.9 GB order index, over the default
+    # 8 GiB budget of its context: its run has no index and is evaluated by
+    # the direct kernel, the other runs by the batched index kernel, in the
+    # same call; a batched EBIC run equals the oracle's.  Device-side steps
+    # need every run's index and refuse the batch.
+    rng = np.random.default_rng(33)
+    big = rng.standard_normal((60000, 1200)).astype(np.float32)
+    small = [rng.standard_normal((300, 14)).astype(np.float32),
+             synth.adversarial_matrix(rng, 500, 10)]
+    mats_ = [small[0], big, small[1]]
+    with E.Batch(mats_) as b:
+        _note("evaluate with a directly evaluated run")
+        for k, neg in ((0, False), (1, True), (5, True)):
+            pops = [synth.pack_cbf(synth.random_population(rng, a.shape[1], 40, 2, 8))
+                    for a in mats_]
+            got = b.evaluate(pops, sigma=9, max_violations=k, negative_trends=neg,
+                             want_masks=True)
+            _check_runs(mats_, pops, got, 9, k, neg)
+        cfg = E.EvolveConfig(population=40, len_min=3, len_max=6, eval=E.Trend(9),
+                             expand=E.Trend(9, 1, True))
+        _note("batched run with a directly evaluated run")
+        res = b.evolve([5, 6, 7], 2, cfg, host_threads=2)
+        for r, (a, s) in enumerate(zip(mats_, (5, 6, 7))):
+            op = oev.EvolveParams(population=40, len_min=3, len_max=6, eval=oev.TrendParams(9),
+                                  expand=oev.TrendParams(9, 1, True))
+            ref = oev.evolve(a, s, 2, op)
+            assert [x["cols"] for x in res[r].biclusters] == [x["cols"] for x in ref.biclusters]
+            for x, y in zip(res[r].biclusters, ref.biclusters):
+                assert x["count"] == y["count"] and x["fitness"] == y["fitness"]
+                assert np.array_equal(x["mask_words"], y["mask_words"])
+        with pytest.raises(E.EbicError):
+            b.evolve([5, 6, 7], 1, cfg, device_steps=True)
