@@ -20,9 +20,10 @@ candidates) on the same population; its exact per-row decision depths also
 give the algorithmic byte counts used for the roofline.
 
 The line also carries `value_amortized` (the one-time index build spread
-over the workload's generations) and two sub-results measured in the same
-run: `wide` (5000 x 1000, P = 4096) and `batched` (64 runs of uneven shape,
-one launch per step); `--no-sub` skips them.
+over the workload's generations) and three sub-results measured in the same
+run: `wide` (5000 x 1000, P = 4096), `batched` (64 runs of uneven shape,
+one launch per step) and `surrogate` (20000 x 500, plain EBIC against the
+screened runs over 300 generations, three seeds); `--no-sub` skips them.
 """
 from __future__ import annotations
 
@@ -398,6 +399,39 @@ def recovery_vs_planted(ebic, res, planted, n_rows, dev):
 
 
 def run_surrogate(args):
+    """The surrogate comparison as the line of `--workload surrogate`."""
+    print(json.dumps(surrogate_comparison(args)), flush=True)
+
+
+def surrogate_subresult(args):
+    """The surrogate comparison, condensed for the default line: per variant
+    the speedup to F* (geometric mean over the seeds), the mean time per
+    generation and the mean recovery."""
+    full = surrogate_comparison(args)
+    runs = full["runs"]
+    keys = {"plain": "plain", "learned": "surrogate", "two_stage": "surrogate_two_stage",
+            "exact_ranked": "exact_ranked_screen"}
+
+    def mean(k, f):
+        return round(float(np.mean([f(r[k]) for r in runs])), 4)
+    return {
+        "workload": full["config"]["workload"], "seeds": full["config"]["seeds"],
+        "metric": full["metric"], "unit": full["unit"],
+        "learned_speedup_at_f_star": full["value"],
+        "two_stage_speedup_at_f_star": full["two_stage_speedup_at_f_star"],
+        "exact_ranked_screen_speedup_at_f_star": full["exact_ranked_screen_speedup_at_f_star"],
+        "ms_per_generation": {n: mean(k, lambda x: x["wall_s"] * 1e3 / x["generations"])
+                              for n, k in keys.items()},
+        "recovery": {n: mean(k, lambda x: x["recovery"]) for n, k in keys.items()},
+        "best_fitness": {n: mean(k, lambda x: x.get("best", 0.0)) for n, k in keys.items()
+                         if n != "plain"},
+        "f_star": round(float(np.mean([r["f_star"] for r in runs])), 4),
+        "mlp_step_ms": full["roofline"]["ms_per_step"],
+        "mlp_roofline_frac": full["roofline"]["frac"],
+    }
+
+
+def surrogate_comparison(args):
     """Plain EBIC against the surrogate-screened run on the same matrix and
     seeds: wall time until each run first holds a candidate of fitness >= F*
     (F* = the plain run's best), and recovery of the final top lists."""
@@ -564,7 +598,7 @@ def run_surrogate(args):
                             "exact_evaluate": round(t_exact * 1e3, 3),
                             "rows_at_equal_cost_if_linear_in_rows": int(w.n_rows * t_mlp / t_exact)},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def wide_subresult(args, dev):
@@ -882,6 +916,8 @@ def main():
         out["wide"] = wide_subresult(args, dev)
         log("sub-result: batched workload")
         out["batched"] = batched_subresult(args)
+        log("sub-result: surrogate workload")
+        out["surrogate"] = surrogate_subresult(args)
     print(json.dumps(out), flush=True)
 
 
