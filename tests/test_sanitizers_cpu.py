@@ -35,6 +35,23 @@ def test_host_side_under_sanitizers(tmp_path):
     assert "host driver ok" in _run(exe)
 
 
+def test_host_side_under_thread_sanitizer(tmp_path):
+    # data races in the host threads of screened runs (persistent helper
+    # threads drawing the pool's shares, hashing the pool in parallel)
+    exe = str(tmp_path / "host_driver_tsan")
+    cmd = (["g++", "-std=c++17", "-fsanitize=thread", "-g", "-O1",
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+            os.path.join(HERE, "sanitize", "host_driver.cpp"),
+            os.path.join(CSRC, "ebic_evolve.cpp"), os.path.join(CSRC, "ebic_checkpoint.cpp"),
+            "-o", exe, "-lpthread"])
+    subprocess.run(cmd, check=True, capture_output=True, timeout=600)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1:second_deadlock_stack=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert "host driver ok" in r.stdout
+    assert "WARNING: ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+
+
 def test_oracle_under_sanitizers(tmp_path):
     exe = str(tmp_path / "oracle_driver")
     cmd = (["gcc", "-std=c11", "-fopenmp"] + SAN +
