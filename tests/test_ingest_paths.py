@@ -301,3 +301,34 @@ def test_index_wide_matrices_sampled_pairs(E, m):
         _note(f"wide m={m} n={n}")
         _check_pairs(E, ctx, a, P, Q, sigma=7)
         assert ctx.info()["index_ties"] == 1
+
+
+def test_concurrent_index_builds_share_the_build_scratch(E):
+    # Contexts built from several host threads at once (the build scratch of
+    # ranks and bit-planes is shared per device and grows for the largest
+    # matrix); every index equals the definition.
+    import threading
+    rng = np.random.default_rng(41)
+    shapes = [(3000, 40), (9000, 120), (700, 300), (20000, 64), (1500, 17), (5000, 200)]
+    mats_ = [rng.standard_normal(sh).astype(np.float32) for sh in shapes]
+    mats_[2][5, 7] = mats_[2][5, 9]
+    pairs = [rng.integers(0, a.shape[1], size=(300, 2)) for a in mats_]
+    errors, done = [], {}
+
+    def work(i):
+        try:
+            ctx = E.Context(mats_[i], path="index")   # builds the index now
+            done[i] = (ctx, pairs[i][:, 0].copy(), pairs[i][:, 1].copy())
+        except Exception as ex:   # reported below
+            errors.append(ex)
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(mats_))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for i, (ctx, P, Q) in sorted(done.items()):
+        _note(f"concurrent build {mats_[i].shape}")
+        _check_pairs(E, ctx, mats_[i], P, Q, sigma=4)
+        assert ctx.info()["index_built"] == 1
+        ctx.close()
