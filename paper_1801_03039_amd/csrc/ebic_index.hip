@@ -26,7 +26,9 @@
 //
 // The compare step stores 512 contiguous bytes per wave and order row, and
 // issues about 2 ALU operations per plane and half-word, so the build is
-// bound by its index writes rather than by its comparisons.  Matrices with
+// bound by its index writes rather than by its comparisons.  The order words
+// are stored non-temporally: nothing reads them before the build ends, and
+// streaming them past the caches keeps the planes there.  Matrices with
 // more than kRankMaxCols columns keep the direct ballot build of
 // ebic_kernels.hip.
 #include "ebic_device.h"
@@ -351,8 +353,8 @@ __global__ __launch_bounds__(kBlock) void index_compare_kernel(
     };
     auto store = [&](int32_t p, int32_t q, uint64_t lt, uint64_t rev) {
         if (word_ok) {
-            (idx + ((int64_t)p * m + q) * wpad)[lw] = lt;
-            if (q != p) (idx + ((int64_t)q * m + p) * wpad)[lw] = rev;
+            __builtin_nontemporal_store(lt, idx + ((int64_t)p * m + q) * wpad + lw);
+            if (q != p) __builtin_nontemporal_store(rev, idx + ((int64_t)q * m + p) * wpad + lw);
         }
     };
     uint64_t pnan[PW];
