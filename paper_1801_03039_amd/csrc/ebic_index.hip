@@ -51,15 +51,22 @@ __device__ __forceinline__ uint32_t order_key(float x) {
 }
 
 // The value of lane (lane ^ X): DPP for the patterns that stay inside a
-// row of 16 lanes and have one (quad permutations, row mirrors), a
-// swizzle for other patterns within 32 lanes, a permute across the halves.
+// row of 16 lanes and have one (quad permutations, row mirrors, the
+// rotation by 8; for X = 4 two row shifts, each writing the banks of four
+// lanes that read from its side), a swizzle for other patterns within 32
+// lanes, a permute across the halves.
 template <int X>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
     const int s = (int)v;
     if constexpr (X == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0xB1, 0xF, 0xF, false);
     else if constexpr (X == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x4E, 0xF, 0xF, false);
     else if constexpr (X == 3) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x1B, 0xF, 0xF, false);
+    else if constexpr (X == 4) {
+        const int up = __builtin_amdgcn_update_dpp(0, s, 0x104, 0xF, 0x5, false);   // row_shl:4
+        return (uint32_t)__builtin_amdgcn_update_dpp(up, s, 0x114, 0xF, 0xA, false);  // row_shr:4
+    }
     else if constexpr (X == 7) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x141, 0xF, 0xF, false);
+    else if constexpr (X == 8) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x128, 0xF, 0xF, false);
     else if constexpr (X == 15) return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x140, 0xF, 0xF, false);
     else if constexpr (X < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle(s, 0x1F | (X << 10));
     else return (uint32_t)__shfl_xor(s, X);
@@ -92,8 +99,18 @@ __device__ __forceinline__ void bitonic_halves(uint32_t (&x)[E], int lg) {
         } else {
             constexpr int dl = d / E;
             const uint32_t keep = (lg & dl) ? ~0u : 0u;   // upper lanes keep the larger
+            if constexpr (dl == 16) {
+                // rows of 16 lanes swap in pairs: each lane then holds both
+                // keys of its pair, and min or max needs no order of the two
 #pragma unroll
-            for (int e = 0; e < E; ++e) x[e] = med3_u32(x[e], lane_xor<dl>(x[e]), keep);
+                for (int e = 0; e < E; ++e) {
+                    const auto two = __builtin_amdgcn_permlane16_swap(x[e], x[e], false, false);
+                    x[e] = med3_u32(two[0], two[1], keep);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = med3_u32(x[e], lane_xor<dl>(x[e]), keep);
+            }
         }
         bitonic_halves<E, LD - 1>(x, lg);
     }
@@ -170,12 +187,9 @@ __global__ __launch_bounds__(kBlock) void index_rank_kernel(const float *__restr
         nan_seen |= in && k == kNanKey;
         x[e] = in ? k : kNanKey;
     }
-    constexpr bool kKeep = E <= 16;   // keep the row's keys for the rank search
-    uint32_t o[kKeep ? E : 1];
-    if constexpr (kKeep) {
+    uint32_t o[E];   // the row's keys, kept for the rank search
 #pragma unroll
-        for (int e = 0; e < E; ++e) o[e] = x[e];
-    }
+    for (int e = 0; e < E; ++e) o[e] = x[e];
 
     // Bitonic sort of the row's M slots, ascending; slot j = lg * E + e.
     bitonic_merges<E, 1, LOGM>(x, lg);
@@ -200,10 +214,7 @@ __global__ __launch_bounds__(kBlock) void index_rank_kernel(const float *__restr
     uint32_t rk[E / 2];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int32_t j = lg * E + e;
-        uint32_t key;
-        if constexpr (kKeep) key = o[e];
-        else key = j < m ? order_key(a[(int64_t)min(j, m - 1) * npad + r]) : kNanKey;
+        const uint32_t key = o[e];
         uint32_t pos = 0;   // number of sorted keys below `key`
 #pragma unroll
         for (int ls = LOGM - 1; ls >= 0; --ls)

@@ -276,11 +276,13 @@ def test_index_ties_confined_to_some_words(E):
         assert ctx.info()["index_ties"] == int(any_tie)
 
 
-@pytest.mark.parametrize("m", [200, 1025, 2048, 2049])
+@pytest.mark.parametrize("m", [200, 300, 700, 1025, 2048, 2049])
 def test_index_wide_matrices_sampled_pairs(E, m):
     # Wide matrices: 1025-2048 columns take the rank build's 32 keys per
-    # lane, 2049 the direct ballot build.  Pairs are sampled (all pairs of
-    # the first 40 columns, pairs with the last column, random pairs), with
+    # lane, 2049 the direct ballot build; 300 and 700 columns rank several
+    # consecutive rows per lane group, here with a row count (145) that
+    # leaves a group part-filled.  Pairs are sampled (all pairs of the
+    # first 40 columns, pairs with the last column, random pairs), with
     # ties and a NaN planted in the first word and an odd word count.
     rng = np.random.default_rng(m)
     n = 64 * 2 + 17
