@@ -158,33 +158,54 @@ size_t run_table_bytes(int32_t n_runs) {
     return sizeof(IndexRun) * (size_t)n_runs + sizeof(uint32_t) * ((size_t)n_runs + 1);
 }
 
-// Fills the run table for a request (tiles of 256 lanes with `words` 64-row
-// words each); returns the total number of tiles.  With `whole`, a run
-// whose candidates take at most 256 lanes each gets tiles of whole
-// candidates (as many as fit); other runs, or all without it, get tiles of
-// 256 consecutive (candidate, word-group) items.
 // Whether run r of request q is evaluated by the batched index kernel (else
 // by the direct kernel after it).
 bool via_index(const ebic_batch *b, const Request &q, int32_t r) {
     return !b->direct[(size_t)r] && q.params->max_violations <= kIndexMaxViolations;
 }
 
+// Fills the run table for a request (tiles of 256 lanes with `words` 64-row
+// words each); returns the total number of tiles.  With `whole`, a run
+// whose candidates take at most 256 lanes each gets tiles of whole
+// candidates (as many as fit); other runs, or all without it, get tiles of
+// 256 consecutive (candidate, word-group) items.  Table entries are in tile
+// order, which is not run order.
 uint64_t fill_runs(ebic_batch *b, const Request &q, int32_t words, int32_t whole) {
     const int32_t R = (int32_t)b->ctx.size();
-    int64_t cand = 0, maskw = 0;
-    uint64_t tiles = 0;
+    std::vector<int64_t> cand((size_t)R), maskw((size_t)R);
+    std::vector<int32_t> cpw((size_t)R), order((size_t)R);
+    int64_t c0 = 0, m0 = 0;
     for (int32_t r = 0; r < R; ++r) {
+        const ebic_ctx *c = b->ctx[(size_t)r];
+        cand[(size_t)r] = c0;
+        maskw[(size_t)r] = m0;
+        c0 += q.P[(size_t)r];
+        if (q.masks) m0 += (int64_t)q.P[(size_t)r] * 2 * c->W;
+        const uint64_t items = (uint64_t)((c->W + words - 1) / words);
+        cpw[(size_t)r] = (whole && items <= 256) ? (int32_t)(256 / items) : 0;
+        order[(size_t)r] = r;
+    }
+    // Runs with more candidates per tile first: such a tile lasts as long as
+    // the longest series among its candidates, so these tiles are the long
+    // ones, and the launch ends on the short tiles of tall runs (measured
+    // 0.1056-0.1077 ms per launch against 0.1093-0.1095 in run order and
+    // 0.1104-0.1107 in the reverse order).  Each run's outputs stay where
+    // its first candidate and mask word say.
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return std::max(cpw[(size_t)x], 1) > std::max(cpw[(size_t)y], 1);
+    });
+    uint64_t tiles = 0;
+    for (int32_t i = 0; i < R; ++i) {
+        const int32_t r = order[(size_t)i];
         ebic_ctx *c = b->ctx[(size_t)r];
         // a directly evaluated run keeps its place in the launch but gets no tiles
         const int32_t P = via_index(b, q, r) ? q.P[(size_t)r] : 0;
         const uint64_t items = (uint64_t)((c->W + words - 1) / words);
-        const int32_t cpw = (whole && items <= 256) ? (int32_t)(256 / items) : 0;
-        b->h_runs[r] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P, cand,
-                                maskw, cpw, 0};
-        b->h_tile_base[r] = (uint32_t)tiles;
-        tiles += cpw ? ((uint64_t)P + cpw - 1) / cpw : ((uint64_t)P * items + 255) / 256;
-        cand += q.P[(size_t)r];
-        if (q.masks) maskw += (int64_t)q.P[(size_t)r] * 2 * c->W;
+        const int32_t k = cpw[(size_t)r];
+        b->h_runs[i] = IndexRun{c->d_idx, c->d_tie, c->d_log, c->n, c->W, c->wpad, c->m, P,
+                                cand[(size_t)r], maskw[(size_t)r], k, 0};
+        b->h_tile_base[i] = (uint32_t)tiles;
+        tiles += k ? ((uint64_t)P + k - 1) / k : ((uint64_t)P * items + 255) / 256;
     }
     b->h_tile_base[R] = (uint32_t)tiles;
     return tiles;
