@@ -10,19 +10,20 @@
 //
 //   1. rank   each row's values become order-preserving 32-bit keys; a wave
 //             sorts them (bitonic network, 16 keys per lane up to 1024
-//             columns, 32 up to 2048) and every column's rank is the number of smaller
-//             keys in the row (a binary search of the sorted row).  Equal
-//             values share a rank.  A row with two equal values or a NaN
-//             flags its 64-row word.
+//             columns, 32 up to 2048) and every column's rank is the number
+//             of smaller keys in the row (a binary search of the sorted
+//             row).  Equal values share a rank.  A row with two equal values
+//             or a NaN flags its 64-row word.
 //   2. planes each (column, word) becomes b bit-planes of its rows' ranks
 //             (b = rank bits) plus one plane of its NaN rows.
 //   3. compare lane = word: lt(p,q) = the rows whose rank in p is below the
 //             rank in q, from the b planes of p and q, least significant
 //             first (at each plane the rows where the planes differ take q's
-//             bit, the others keep what lower planes decided).  Words of an
-//             unflagged word are exact complements: lt(q,p) = ~lt(p,q) on
-//             valid rows.  Flagged words compute lt(q,p) the same way, clear
-//             NaN rows from both, and report tied pairs.
+//             bit, the others keep what lower planes decided).  In a wave
+//             with no flagged word the two orders are exact complements:
+//             lt(q,p) = ~lt(p,q) on valid rows.  Otherwise lt(q,p) is formed
+//             the same way, NaN rows are cleared from both, and tied pairs
+//             are reported.
 //
 // The compare step stores 512 contiguous bytes per wave and order row, and
 // issues about 2 ALU operations per plane and half-word, so the build is
@@ -82,8 +83,9 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
 // two sorted blocks of 2^(LK-1) slots pairs slot j with its mirror
 // j ^ (2^LK - 1), later stages pair j with j ^ 2^LD; in every pair the
 // lower slot keeps the smaller key, so no stage needs a per-lane direction.
-// A pair in two lanes exchanges keys through a lane permutation.  The
-// stages are template recursions, so every distance is a constant.
+// A pair in two lanes exchanges keys through a lane permutation (at
+// distance 16 a swap of 16-lane rows that leaves both keys in each lane).
+// The stages are template recursions, so every distance is a constant.
 template <int E, int LD>
 __device__ __forceinline__ void bitonic_halves(uint32_t (&x)[E], int lg) {
     if constexpr (LD >= 0) {
